@@ -1,0 +1,297 @@
+"""Seeded synthetic inputs for the resistive GRMHD stage update.
+
+This module only draws initial data: primitive fields, the fixed background
+metric and the conductivity.  It holds none of the method's arithmetic (no
+prim2con, no fluxes, no recovery), so both the HIP library and the CPU oracle
+can take their inputs from it.  Every array is float64, field-major
+``[nf, nz_p, ny_p, nx_p]`` with ghost cells, x fastest.
+
+The workloads are seeded analogues of the paper's initial-value problems
+(Sec. IV: 1D shocktube, smooth 3D MHD, a static curved background with a
+magnetised blob, and a batch of 1D current-sheet-like problems); the paper's
+figures carry no data, so no item of them is reproduced.
+
+Primitive order: rho, p, v^x, v^y, v^z, B^x, B^y, B^z, E^x, E^y, E^z, phi, psi, q.
+Metric order: alpha, beta^x, beta^y, beta^z, gamma_xx, gamma_xy, gamma_xz,
+gamma_yy, gamma_yz, gamma_zz, K_xx, K_xy, K_xz, K_yy, K_yz, K_zz.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+NG = 3
+RECON = {"minmod": 0, "mc2": 1, "weno5": 2}
+BC = {"periodic": 0, "copy": 1}
+
+
+@dataclass
+class Workload:
+    name: str
+    n: tuple            # interior cells (nx, ny, nz)
+    active: int         # bit d set: fluxes and ghosts along d
+    dx: tuple
+    x0: tuple           # centre of the first interior cell
+    bc: tuple
+    gamma_ad: float
+    recon: int
+    dt: float
+    steps: int
+    P: np.ndarray       # [14, nz_p, ny_p, nx_p]
+    sigma: np.ndarray   # [nz_p, ny_p, nx_p]
+    metric: np.ndarray | None = None   # [16, ...] or None (flat)
+    kappa: float = 1.0
+    extra: dict = field(default_factory=dict)
+
+    @property
+    def ghosts(self):
+        return tuple(NG if (self.active >> d) & 1 else 0 for d in range(3))
+
+    @property
+    def padded(self):
+        g = self.ghosts
+        return (self.n[2] + 2 * g[2], self.n[1] + 2 * g[1], self.n[0] + 2 * g[0])
+
+    @property
+    def interior(self):
+        g = self.ghosts
+        return tuple(slice(g[d], g[d] + self.n[d]) for d in (2, 1, 0))
+
+    @property
+    def n_interior(self):
+        return int(self.n[0]) * int(self.n[1]) * int(self.n[2])
+
+
+def _coords(n, active, x0, dx):
+    """Cell-centre coordinates of the padded grid, as broadcastable (z, y, x)."""
+    out = []
+    for d in range(3):
+        g = NG if (active >> d) & 1 else 0
+        idx = np.arange(-g, n[d] + g, dtype=np.float64)
+        out.append(x0[d] + idx * dx[d])
+    x, y, z = out
+    return x[None, None, :], y[None, :, None], z[:, None, None]
+
+
+def _pad(a, n, active, mode):
+    """Embed an interior array (nz, ny, nx) into the padded shape."""
+    widths = []
+    for d in (2, 1, 0):
+        g = NG if (active >> d) & 1 else 0
+        widths.append((g, g))
+    return np.pad(a, widths, mode=mode)
+
+
+def _flat_metric_fields(shape):
+    m = np.zeros((16,) + shape)
+    m[0] = 1.0
+    m[4] = m[7] = m[9] = 1.0
+    return m
+
+
+# ----------------------------------------------------------------- config 1
+def shocktube(seed=101, sigma0=1e6, n=400, cfl=0.5, t_end=0.4) -> Workload:
+    """1D resistive Riemann problem on x in [-0.5, 0.5], flat, Gamma = 2,
+    minmod, copy boundaries; left/right states drawn from the seed (the
+    paper's shocktube of Sec. IV.A with randomised states)."""
+    rng = np.random.default_rng(seed)
+    rhoL, rhoR, pL, pR = rng.uniform(0.1, 1.0, 4)
+    ByL, BzL, ByR, BzR = rng.uniform(-1.0, 1.0, 4)
+    dx = 1.0 / n
+    nn = (n, 1, 1)
+    x, _, _ = _coords(nn, 1, (-0.5 + 0.5 * dx, 0.0, 0.0), (dx, 1.0, 1.0))
+    left = (x < 0.0)[None]
+    shape = (1, 1, n + 2 * NG)
+    P = np.zeros((14,) + shape)
+    P[0] = np.where(left, rhoL, rhoR)
+    P[1] = np.where(left, pL, pR)
+    P[5] = 0.5
+    P[6] = np.where(left, ByL, ByR)
+    P[7] = np.where(left, BzL, BzR)
+    sigma = np.full(shape, float(sigma0))
+    dt = cfl * dx
+    steps = int(round(t_end / dt))
+    return Workload("shocktube_1d_400", nn, 1, (dx, 1.0, 1.0), (-0.5 + 0.5 * dx, 0.0, 0.0), (1, 1, 1), 2.0,
+                    RECON["minmod"], t_end / steps, steps, P, sigma, None,
+                    extra=dict(seed=seed, sigma0=sigma0, cfl=cfl))
+
+
+# ----------------------------------------------------------------- config 2
+_KSET = None
+
+
+def _kset():
+    global _KSET
+    if _KSET is None:
+        r = np.arange(-4, 5)
+        k = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+        nrm = np.sqrt((k ** 2).sum(1))
+        _KSET = k[(nrm > 0) & (nrm <= 4.0)]
+    return _KSET
+
+
+def _modes(rng, nmodes=8):
+    ks = _kset()
+    k = ks[rng.integers(0, len(ks), nmodes)]
+    a = rng.uniform(-1.0, 1.0, nmodes)
+    ph = rng.uniform(0.0, 2.0 * math.pi, nmodes)
+    return k, a, ph
+
+
+def _mode_sum(k, a, ph, x, y, z):
+    s = 0.0
+    for m in range(len(a)):
+        s = s + a[m] * np.cos(2 * math.pi * (k[m, 0] * x + k[m, 1] * y + k[m, 2] * z) + ph[m])
+    return s
+
+
+def _mode_grad(k, a, ph, x, y, z):
+    g = [0.0, 0.0, 0.0]
+    for m in range(len(a)):
+        s = -a[m] * 2 * math.pi * np.sin(2 * math.pi * (k[m, 0] * x + k[m, 1] * y + k[m, 2] * z) + ph[m])
+        for d in range(3):
+            g[d] = g[d] + k[m, d] * s
+    return g
+
+
+def periodic_box(n=128, seed=201, cfl=0.4, steps=10) -> Workload:
+    """Smooth 3D periodic box [0,1)^3, flat, Gamma = 4/3, WENO5: density,
+    pressure and velocity from random Fourier modes (|k| <= 4), B from the
+    analytic curl of a random vector potential (rms |B| = 0.5), E = -v x B,
+    and a smoothed log-uniform conductivity in [1, 1e6]."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    nn = (n, n, n)
+    x, y, z = _coords(nn, 7, (0.5 * dx,) * 3, (dx,) * 3)
+    shape = (n + 2 * NG,) * 3
+    P = np.zeros((14,) + shape)
+
+    def norm_modes():
+        k, a, ph = _modes(rng)
+        M = _mode_sum(k, a, ph, x, y, z)
+        inner = M[NG:-NG, NG:-NG, NG:-NG]
+        return M / np.abs(inner).max()
+
+    P[0] = 1.0 + 0.3 * norm_modes()
+    P[1] = 0.5 * (1.0 + 0.2 * norm_modes())
+    for d in range(3):
+        P[2 + d] = (0.5 / math.sqrt(3.0)) * norm_modes()
+    grads = []
+    for d in range(3):
+        k, a, ph = _modes(rng)
+        grads.append(_mode_grad(k, a, ph, x, y, z))
+    # B = curl A, with grads[c][j] = d_j A_c
+    Bx = grads[2][1] - grads[1][2]
+    By = grads[0][2] - grads[2][0]
+    Bz = grads[1][0] - grads[0][1]
+    Bx, By, Bz = (np.broadcast_to(b, shape) for b in (Bx, By, Bz))
+    inner = (slice(NG, -NG),) * 3
+    rms = math.sqrt(float(np.mean(Bx[inner] ** 2 + By[inner] ** 2 + Bz[inner] ** 2)))
+    P[5], P[6], P[7] = Bx * (0.5 / rms), By * (0.5 / rms), Bz * (0.5 / rms)
+    vx, vy, vz = P[2], P[3], P[4]
+    P[8] = -(vy * P[7] - vz * P[6])
+    P[9] = -(vz * P[5] - vx * P[7])
+    P[10] = -(vx * P[6] - vy * P[5])
+    s = rng.standard_normal((n, n, n))
+    for _ in range(3):
+        for ax in range(3):
+            s = 0.25 * np.roll(s, 1, ax) + 0.5 * s + 0.25 * np.roll(s, -1, ax)
+    s = (s - s.min()) / (s.max() - s.min())
+    sigma = _pad(10.0 ** (6.0 * s), nn, 7, "wrap")
+    return Workload(f"periodic_box_{n}^3", nn, 7, (dx,) * 3, (0.5 * dx,) * 3, (0, 0, 0), 4.0 / 3.0,
+                    RECON["weno5"], cfl * dx, steps, P, sigma, None, extra=dict(seed=seed, cfl=cfl))
+
+
+# ----------------------------------------------------------------- config 3
+def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20) -> Workload:
+    """Static conformally flat background on [-1,1]^3 (gamma_ij = psi^4
+    delta_ij, psi = 1 + 0.1 exp(-r^2/0.25), alpha = 1 - 0.3 exp(-r^2/0.25),
+    zero shift and extrinsic curvature), a seeded density blob
+    rho = 1e-3 + exp(-r^2/0.09)(1 + 0.05 noise), p = 100 rho^2, v = E = 0,
+    a poloidal B (max |B| = 1e-3) confined to r < 0.4 from the discrete curl
+    of A = a(r) (-y, x, 0), and sigma = 1e6 rho/rho_max + 1; Gamma = 2."""
+    rng = np.random.default_rng(seed)
+    dx = 2.0 / n
+    nn = (n, n, n)
+    x0 = -1.0 + 0.5 * dx
+    x, y, z = _coords(nn, 7, (x0,) * 3, (dx,) * 3)
+    shape = (n + 2 * NG,) * 3
+    r2 = x * x + y * y + z * z
+    met = np.zeros((16,) + shape)
+    bump = np.exp(-r2 / 0.25)
+    psi = 1.0 + 0.1 * bump
+    met[0] = 1.0 - 0.3 * bump
+    met[4] = met[7] = met[9] = psi ** 4
+    noise = _pad(rng.uniform(-1.0, 1.0, (n, n, n)), nn, 7, "edge")
+    P = np.zeros((14,) + shape)
+    P[0] = 1e-3 + np.exp(-r2 / 0.09) * (1.0 + 0.05 * noise)
+    P[1] = 100.0 * P[0] ** 2
+
+    def a_of(xx, yy, zz):
+        rr = xx * xx + yy * yy + zz * zz
+        return np.where(rr < 0.16, (0.16 - rr) ** 2, 0.0)
+
+    h = dx
+
+    def A(xx, yy, zz):
+        a = a_of(xx, yy, zz)
+        return -a * yy, a * xx
+
+    Ax_yp, Ay_yp = A(x, y + h, z)
+    Ax_ym, Ay_ym = A(x, y - h, z)
+    Ax_zp, Ay_zp = A(x, y, z + h)
+    Ax_zm, Ay_zm = A(x, y, z - h)
+    Ax_xp, Ay_xp = A(x + h, y, z)
+    Ax_xm, Ay_xm = A(x - h, y, z)
+    Bx = -(Ay_zp - Ay_zm) / (2 * h)
+    By = (Ax_zp - Ax_zm) / (2 * h)
+    Bz = (Ay_xp - Ay_xm) / (2 * h) - (Ax_yp - Ax_ym) / (2 * h)
+    Bx, By, Bz = (np.broadcast_to(b, shape) for b in (Bx, By, Bz))
+    inner = (slice(NG, -NG),) * 3
+    bmax = float(np.sqrt(Bx[inner] ** 2 + By[inner] ** 2 + Bz[inner] ** 2).max())
+    scale = 1e-3 / bmax
+    P[5], P[6], P[7] = Bx * scale, By * scale, Bz * scale
+    rho_max = float(P[0][inner].max())
+    sigma = 1e6 * P[0] / rho_max + 1.0
+    return Workload(f"curved_blob_{n}^3_{recon}", nn, 7, (dx,) * 3, (x0,) * 3, (1, 1, 1), 2.0, RECON[recon],
+                    cfl * dx, steps, P, sigma, met, extra=dict(seed=seed, cfl=cfl))
+
+
+# ----------------------------------------------------------------- config 5
+def sheet_batch(nprob=64, n=2048, seed=501, target_seed=502, cfl=0.25, steps=200) -> Workload:
+    """Batch of independent 1D flat problems on x in [-0.5, 0.5] (a batch
+    of current sheets with smooth noise): B^y = tanh(x/w) + 0.05 noise,
+    rho = 1, p ~ U[0.1, 1] per problem, v = E = 0, per-problem sigma =
+    10^U[0,3]; Gamma = 4/3, WENO5, copy boundaries.  The batch index is the
+    y dimension, which carries no flux."""
+    rng = np.random.default_rng(seed)
+    dx = 1.0 / n
+    nn = (n, nprob, 1)
+    x0 = -0.5 + 0.5 * dx
+    x = x0 + dx * np.arange(-NG, n + NG)
+    shape = (1, nprob, n + 2 * NG)
+    P = np.zeros((14,) + shape)
+    w = rng.uniform(0.02, 0.1, nprob)
+    pb = rng.uniform(0.1, 1.0, nprob)
+    sig = 10.0 ** rng.uniform(0.0, 3.0, nprob)
+    for b in range(nprob):
+        g = rng.standard_normal(8)
+        ph = rng.uniform(0.0, 2 * math.pi, 8)
+        nz = sum((g[m - 1] / m) * np.sin(2 * math.pi * m * (x + 0.5) + ph[m - 1]) for m in range(1, 9))
+        nz = nz / np.abs(nz[NG:-NG]).max()
+        P[6, 0, b] = np.tanh(x / w[b]) + 0.05 * nz
+        P[1, 0, b] = pb[b]
+    P[0] = 1.0
+    sigma = np.broadcast_to(sig[None, :, None], shape).copy()
+    trng = np.random.default_rng(target_seed)
+    sig_t = 10.0 ** trng.uniform(0.0, 3.0, nprob)
+    return Workload(f"sheet_batch_{nprob}x{n}", nn, 1, (dx, 1.0, 1.0), (x0, 0.0, 0.0), (1, 1, 1), 4.0 / 3.0,
+                    RECON["weno5"], cfl * dx, steps, P, sigma, None,
+                    extra=dict(seed=seed, sigma_problem=sig, sigma_target=sig_t))
+
+
+def by_name(name: str, **kw) -> Workload:
+    return {"shocktube": shocktube, "periodic_box": periodic_box, "curved_blob": curved_blob,
+            "sheet_batch": sheet_batch}[name](**kw)
