@@ -1,0 +1,245 @@
+#!/usr/bin/env python3
+"""Benchmark of the resistive GRMHD IMEX-SSP2(2,2,2) stage on one MI355X.
+
+Metric: zone-updates/s per IMEX stage (interior cells x stage-2 applications
+per second) on the 256^3 static curved background with a magnetised blob,
+FP64, WENO5 + HLLE, after 10 steps of evolution (so that the stiff recovery
+does real work).  One timed "step" is one application of IMEX stage 2: ghost
+fill, reconstruction, HLLE fluxes, flux divergence + sources + RK combination
+and the coupled implicit-E / primitive recovery, i.e. every row of the hot
+path.  A full IMEX step (two such flux stages plus the pointwise stage 1) is
+timed as well and reported beside it.
+
+Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "zone-updates/s per IMEX stage, FP64 vs mixed at 256^3; fwd+adjoint s/step"
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_FP64_VECTOR_TFLOPS = 78.6
+
+# Executed FP64 work per interior cell and launch of each kernel class for
+# the 256^3 WENO5 curved workload (from the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
+# counters, FMA = 2 flops, 64 lanes per wave instruction), and algorithmic HBM
+# bytes per interior cell (each word read or written once).
+FLOPS_PER_CELL = {}
+BYTES_PER_CELL = {
+    # P 14 + metric alpha, gamma 7 + sigma 1 read, rhs 14 written
+    "flux_x": 8 * (14 + 7 + 1 + 14),
+    # as x, plus the read-modify-write of rhs
+    "flux_y": 8 * (14 + 7 + 1 + 14 + 14),
+    "flux_z": 8 * (14 + 7 + 1 + 14 + 14),
+    # rhs 14, U^n 14, P(1) 14, R1 3, sigma 1, metric 7 read; U(2) 14, P(2) 14, R2 3 written
+    "update_stage2": 8 * (14 + 14 + 14 + 3 + 1 + 7 + 14 + 14 + 3),
+    # ghost faces only
+    "ghost_fill": 0,
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20, help="timed stage-2 applications")
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256, help="cells per dimension (default: the 256^3 workload)")
+    ap.add_argument("--recon", default="weno5", choices=["weno5", "mc2", "minmod"])
+    ap.add_argument("--evolve", type=int, default=10, help="IMEX steps before timing")
+    ap.add_argument("--full-steps", type=int, default=3, help="timed full IMEX steps (reported beside)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", default="96,96,48", help="oracle sub-box (nx,ny,nz) for cpu_baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also launch a plain device copy of known size (for HBM counter calibration)")
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(w, dt, sample):
+    """The oracle, as it stands, on a sub-box of the same workload: the
+    central nx x ny x nz cells of the seeded initial data with their real
+    neighbours as ghost cells (held fixed), advanced two oracle steps, then
+    one timed oracle stage 2."""
+    import oracle
+
+    oracle.build(force=False)
+    nx, ny, nz = sample
+    N = w.n[0]
+    c = N // 2
+    lo = [c - nx // 2, c - ny // 2, c - nz // 2]
+    sl = (slice(lo[2], lo[2] + nz + 6), slice(lo[1], lo[1] + ny + 6), slice(lo[0], lo[0] + nx + 6))
+    P = np.ascontiguousarray(w.P[(slice(None),) + sl])
+    met = np.ascontiguousarray(w.metric[(slice(None),) + sl])
+    sig = np.ascontiguousarray(w.sigma[sl])
+    x0 = tuple(w.x0[d] + lo[d] * w.dx[d] for d in range(3))
+    og = oracle.make_grid((nx, ny, nz), 7, w.dx, (oracle.BC_GIVEN,) * 3, w.gamma_ad, recon=w.recon, x0=x0)
+    U = oracle.prim2con(og, P, met)
+    for _ in range(2):
+        oracle.step(og, dt, sig, U, P, met)
+    s1 = oracle.stage1(og, dt, sig, U, P, met)
+    t0 = time.perf_counter()
+    s2 = oracle.stage2(og, dt, sig, U, s1["P1"], s1["R1"], met)
+    t = time.perf_counter() - t0
+    cells = nx * ny * nz
+    return {"value": cells / t, "unit": "zone-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"one IMEX stage 2 on the central {nx}x{ny}x{nz} cells of the 256^3 curved-blob "
+                      f"workload (real neighbour ghosts, held fixed), after two oracle steps; "
+                      f"{t:.2f} s, {int(s2['nfail'])} failed cells"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU domain decomposition "
+              f"is a design note, not part of this build.", file=sys.stderr)
+        return 2
+    import torch
+
+    from paper_2510_18968_amd import rmhd
+    from paper_2510_18968_amd import workloads as W
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        return 2
+    rmhd.lib()   # fails loudly if the library is missing
+
+    t0 = time.perf_counter()
+    w = W.curved_blob(n=args.n, recon=args.recon)
+    log(f"inputs generated in {time.perf_counter() - t0:.1f} s: {w.name}, padded {w.padded}")
+    g = rmhd.grid_for(w)
+    met = torch.from_numpy(w.metric).cuda()
+    g.set_metric(met)
+    sig = torch.from_numpy(w.sigma).cuda()
+    P = torch.from_numpy(w.P).cuda()
+    U = g.prim2con(P)
+
+    # CFL time step from the characteristic speeds (static metric: constant)
+    smax = g.max_signal_speed()
+    dt = 0.25 / smax
+    log(f"max signal speed {smax:.6g} -> dt {dt:.6g} (CFL 0.25)")
+
+    t0 = time.perf_counter()
+    for _ in range(args.evolve):
+        g.step(dt, sig, U, P)
+    torch.cuda.synchronize()
+    nfail = g.failures()
+    log(f"{args.evolve} steps in {time.perf_counter() - t0:.2f} s, failed recoveries {nfail}")
+    if nfail:
+        raise SystemExit("recovery failures during evolution")
+
+    # stage-2 inputs at this state
+    P1, R1 = g.empty(), g.empty(3)
+    g.imex_stage(1, dt, sig, U, P, P1, R_out=R1)
+    U2, P2, R2 = g.empty(), g.empty(), g.empty(3)
+
+    def stage2():
+        g.imex_stage(2, dt, sig, U, P1, P2, R_out=R2, R1=R1, U_out=U2)
+
+    for _ in range(args.warmup):
+        stage2()
+    torch.cuda.synchronize()
+    g.timing(True)
+    g.timing_read()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.steps):
+        stage2()
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop)
+    kern = g.timing_read()
+    g.timing(False)
+    nfail = g.failures()
+    if nfail:
+        raise SystemExit(f"{nfail} failed recoveries in the timed stages")
+    ncell = w.n_interior
+    value = ncell * args.steps / (ms * 1e-3)
+    log(f"stage 2: {ms / args.steps:.3f} ms -> {value:.4g} zone-updates/s")
+
+    # full IMEX steps (stage 1 + stage 2 + final), reported beside
+    Uc, Pc = U.clone(), P.clone()
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(args.full_steps):
+        g.step(dt, sig, Uc, Pc)
+    stop.record()
+    torch.cuda.synchronize()
+    ms_step = start.elapsed_time(stop) / max(1, args.full_steps)
+    if g.failures():
+        raise SystemExit("failed recoveries in the full steps")
+
+    if args.calibrate_copy:
+        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")   # 2 GiB
+        b = torch.empty_like(a)
+        for _ in range(2):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
+    dominant = max(per_launch, key=lambda k: kern[k][0])
+    dom_ms = per_launch[dominant]
+    if dominant in FLOPS_PER_CELL:
+        flops = FLOPS_PER_CELL[dominant] * ncell
+        achieved = flops / (dom_ms * 1e-3) / 1e12
+        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None, "kernel": dominant}
+    else:
+        bytes_ = BYTES_PER_CELL.get(dominant, 0) * ncell
+        achieved = bytes_ / (dom_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dominant}
+    roof["kernel_ms"] = dom_ms
+    roof["hbm_gbs_algorithmic"] = BYTES_PER_CELL.get(dominant, 0) * ncell / (dom_ms * 1e-3) / 1e9
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del U, P, U2, P2, P1, R1, R2, Uc, Pc
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(w, dt, tuple(int(x) for x in args.cpu_sample.split(",")))
+        log(f"cpu baseline {cpu['value']:.4g} zone-updates/s in {time.perf_counter() - t0:.1f} s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "zone-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"curved_blob {args.n}^3 {args.recon} FP64: IMEX-SSP2(2,2,2) stage 2 after "
+                               f"{args.evolve} steps (static conformally flat metric, Gamma = 2, "
+                               f"sigma = 1e6 rho/rho_max + 1, CFL 0.25, copy boundaries)",
+                   "n": [args.n] * 3, "recon": args.recon, "dt": dt, "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels_ms_per_launch": per_launch,
+        "full_step": {"ms": ms_step, "zone_updates_per_s_per_stage": 2 * ncell / (ms_step * 1e-3)},
+    }
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,175 @@
+/*
+ * rmhd.h -- C ABI of the MI355X (gfx950) resistive GRMHD stage library.
+ *
+ * The library advances the 14 conserved variables of resistive general-
+ * relativistic MHD on a uniform grid in a fixed 3+1 metric with the
+ * IMEX-SSP2(2,2,2) Runge-Kutta scheme of arXiv:2510.18968 (Sec. III.A,
+ * table imex, eq. IMEX3): reconstruction of the primitives (minmod, MC2,
+ * WENO5), HLLE fluxes with speed-of-light characteristic speeds (Sec. III),
+ * flux divergence plus non-stiff sources (eq. GRRMHD_flux_form), and a
+ * per-cell implicit solve of the stiff Ohm's-law term (eq. 3D_NR) coupled to
+ * the primitive recovery (Sec. III.B).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array pointers are DEVICE pointers (HIP global memory) unless the
+ *    name ends in host_out.  The caller owns every array; the library owns
+ *    only the opaque context.  Scratch memory comes from a caller-provided
+ *    workspace, so the library never allocates device memory itself.
+ *  - Layout: float64, structure of arrays, field-major
+ *    a[f][k][j][i] with i (x) fastest, over the PADDED grid: along every
+ *    active dimension d there are ng = 3 ghost cells on each side, inactive
+ *    dimensions carry none.  Np = prod_d (n[d] + 2 ghost_d).
+ *  - Primitive vector P (14): rho, p, v^x, v^y, v^z, B^x, B^y, B^z,
+ *    E^x, E^y, E^z, phi, psi, q (contravariant, not densitised; v is the
+ *    Eulerian 3-velocity of Sec. II.A).
+ *  - Conserved vector U (14): D, S_x, S_y, S_z, tau, Bcal^x..z, Ecal^x..z,
+ *    Phi, Psi, Qcal (eqs. conserved_dens/_tau/_S and the densitised fields of
+ *    Sec. II.D).  Index f of an EM / cleaning / charge field is the same in P
+ *    and U.
+ *  - Metric fields (Sec. II.A): alpha [Np], beta^i [3][Np], gamma_ij
+ *    [6][Np] in the order xx, xy, xz, yy, yz, zz, K_ij [6][Np] likewise, all
+ *    at cell centres INCLUDING ghost cells (the caller evaluates them there).
+ *  - Every call is asynchronous on the context's HIP stream, except those
+ *    documented as synchronising.  Only interior cells of outputs are
+ *    written; ghost cells of U are never read.
+ *  - Return codes: RMHD_OK or a negative RMHD_E* code.  Argument checks
+ *    happen on the host before any device work (RMHD_EINVAL).  Per-cell
+ *    recovery failures never abort a launch: they set a per-cell status and
+ *    bump a device counter read by rmhd_failures().  rmhd_last_error() gives
+ *    a thread-local message for the last failing call.
+ *  - A context is not thread-safe; separate contexts are independent.
+ */
+#ifndef RMHD_H
+#define RMHD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rmhd_ctx rmhd_ctx;
+
+enum rmhd_status {
+    RMHD_OK = 0,
+    RMHD_EINVAL = -1,   /* invalid argument (checked on the host)             */
+    RMHD_EHIP = -2,     /* a HIP runtime call failed                           */
+    RMHD_ENOCONV = -3,  /* per-cell: recovery did not converge                 */
+    RMHD_EUNPHYS = -4   /* per-cell: unphysical state (rho<=0, v^2>=1, NaN ..) */
+};
+/* per-cell status values written by the recovery: 0 ok, 1 converged at the
+ * iteration cap within 1e-12 (warning), RMHD_ENOCONV, RMHD_EUNPHYS */
+
+enum rmhd_recon { RMHD_RECON_MINMOD = 0, RMHD_RECON_MC2 = 1, RMHD_RECON_WENO5 = 2 };
+enum rmhd_bc { RMHD_BC_PERIODIC = 0, RMHD_BC_COPY = 1 };
+enum rmhd_precision { RMHD_PREC_FP64 = 0, RMHD_PREC_MIXED = 1 };
+
+typedef struct {
+    int32_t n[3];        /* interior cells per dimension; a batch of 1D problems
+                            is n = {cells, problems, 1} with only x active     */
+    int32_t active_mask; /* bit d set: fluxes and ghost cells along d          */
+    int32_t ng;          /* ghost width; must be 3                             */
+    int32_t bc[3];       /* per dimension: RMHD_BC_PERIODIC or RMHD_BC_COPY    */
+    int32_t recon;       /* enum rmhd_recon                                    */
+    int32_t precision;   /* enum rmhd_precision (MIXED: FP32 stencil, FP64
+                            recovery and state)                                */
+    int32_t c2p_maxit;   /* recovery iteration cap (default 500)               */
+    int32_t speed_mode;  /* 0: +-sqrt(gamma^dd) - beta^d/alpha as printed in
+                            Sec. III; 1: alpha sqrt(gamma^dd) -+ beta^d        */
+    double x0[3];        /* centre of the first interior cell                  */
+    double dx[3];        /* cell widths                                        */
+    double gamma_ad;     /* ideal-gas adiabatic index Gamma (Sec. III.B)        */
+    double kappa;        /* divergence-cleaning damping (1 in the paper, Sec. IV)*/
+    double c2p_tol;      /* recovery tolerance on |dp|/p and |dv| (1e-14)       */
+} rmhd_grid_desc;
+
+/* Buffers of one IMEX stage (Sec. III.A, eq. IMEX3).  [3][Np] arrays hold the
+ * stiff E source R_E of a stage, recovered from the stage equation as
+ * (Ecal(s) - Ecal*)/(gamma dt); [14][Np] arrays are U or P.
+ *   stage 1 (implicit only):   in U_n, P_in = P^n (guess)
+ *                              out P_out = P(1), R_out = R1, U_out = U(1) (optional)
+ *   stage 2 (explicit + impl.): in U_n, P_in = P(1), R1
+ *                              out U_out = U(2), P_out = P(2), R_out = R2
+ *   stage 3 (final update):    in U_n, U_s = U(2), P_in = P(2), R1, R2
+ *                              out U_out = U^{n+1}, P_out = P^{n+1}
+ * Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  For stage 3,
+ * U_out may alias U_n and P_out may alias nothing else.  status is optional
+ * ([Np] int32, interior cells written). */
+typedef struct {
+    const double* U_n;
+    const double* U_s;
+    double* P_in;
+    const double* R1;
+    const double* R2;
+    double* U_out;
+    double* P_out;
+    double* R_out;
+    int32_t* status;
+} rmhd_stage_bufs;
+
+/* Bytes of device workspace a context needs for this grid (>= 0; 0 on an
+ * invalid descriptor, see rmhd_last_error). */
+size_t rmhd_workspace_bytes(const rmhd_grid_desc* desc);
+
+/* Create a context.  workspace: device memory of at least
+ * rmhd_workspace_bytes(desc) bytes, 256-byte aligned, owned by the caller and
+ * kept alive until rmhd_destroy.  hip_stream: a hipStream_t (NULL = default
+ * stream).  The metric defaults to flat space (alpha = 1, beta = 0,
+ * gamma_ij = delta_ij, K_ij = 0).  Returns RMHD_EINVAL on a bad descriptor. */
+int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes, void* hip_stream, rmhd_ctx** out);
+
+/* Fixed background metric, Sec. II.A (alpha, beta^i, gamma_ij, K_ij at cell
+ * centres including ghosts, layouts above).  beta == NULL means zero shift,
+ * K == NULL zero extrinsic curvature; alpha == NULL and gamma == NULL restore
+ * flat space.  The arrays are referenced, not copied: keep them alive and
+ * unchanged while the context uses them. */
+int rmhd_set_metric(rmhd_ctx* ctx, const double* alpha, const double* beta, const double* gamma, const double* K);
+
+/* Conserved from primitive variables, eqs. conserved_dens, conserved_tau,
+ * conserved_S and the densitised fields of Sec. II.D, at interior cells. */
+int rmhd_prim2con(rmhd_ctx* ctx, const double* P, double* U);
+
+/* Primitive recovery with E fixed, Sec. III.B steps (i)-(v): P is the guess
+ * on input and the result on output (interior cells).  status optional. */
+int rmhd_con2prim(rmhd_ctx* ctx, const double* U, double* P, int32_t* status);
+
+/* One stage of IMEX-SSP2(2,2,2) (table imex, eq. IMEX3), see rmhd_stage_bufs.
+ * sigma: conductivity [Np] (ghost cells are not read). */
+int rmhd_imex_stage(rmhd_ctx* ctx, int stage, double dt, const double* sigma, const rmhd_stage_bufs* bufs);
+
+/* One full IMEX-SSP2(2,2,2) step in place: (U, P) at t -> t + dt.  Stage
+ * buffers live in the workspace. */
+int rmhd_step(rmhd_ctx* ctx, double dt, const double* sigma, double* U, double* P);
+
+/* max over interior cells and active d of max|lambda^d_+-| / dx_d with the
+ * characteristic speeds of Sec. III; a stable step is dt = CFL / value.
+ * Synchronises the stream and writes *host_out. */
+int rmhd_max_signal_speed(rmhd_ctx* ctx, double* host_out);
+
+/* Number of failed per-cell recoveries since the last call (then reset).
+ * Synchronises the stream. */
+int rmhd_failures(rmhd_ctx* ctx, int64_t* host_out);
+
+/* Opt-in per-kernel timing (profiling aid, off by default): with enable != 0
+ * the library brackets every launch with HIP events on the context's stream,
+ * grouped by kernel class: 0 ghost fill, 1 x fluxes, 2 y fluxes, 3 z fluxes,
+ * 4 stage-2 update + stiff recovery, 5 final update + recovery, 6 stage 1,
+ * 7 other pointwise kernels.  rmhd_timing_read synchronises the stream,
+ * writes the summed milliseconds and launch counts of each class since the
+ * last read (arrays of RMHD_TIMING_CLASSES entries) and resets them. */
+#define RMHD_TIMING_CLASSES 8
+int rmhd_timing(rmhd_ctx* ctx, int enable);
+int rmhd_timing_read(rmhd_ctx* ctx, double* ms_out, int64_t* launches_out);
+
+/* Release the context (not the workspace). */
+int rmhd_destroy(rmhd_ctx* ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* rmhd_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RMHD_H */

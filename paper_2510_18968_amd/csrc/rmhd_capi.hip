@@ -1,0 +1,417 @@
+// Host side of the C ABI declared in include/rmhd.h: argument checks,
+// workspace carving and kernel launches on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "rmhd.h"
+#include "rmhd_kernels.hpp"
+
+using namespace rmhd;
+
+struct rmhd_ctx {
+    rmhd_grid_desc desc;
+    Params p;
+    hipStream_t stream;
+    char* ws;
+    size_t ws_bytes;
+    double *rhs, *P1, *R1, *U2, *P2, *R2;
+    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits
+    bool curved;
+    // opt-in launch timing: event pairs per kernel class, reused after a read
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[RMHD_TIMING_CLASSES];
+    size_t used[RMHD_TIMING_CLASSES] = {};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                              \
+    do {                                                                                           \
+        hipError_t e_ = (call);                                                                    \
+        if (e_ != hipSuccess) return fail(RMHD_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+#define LAUNCH_CHECK()                                                                             \
+    do {                                                                                           \
+        hipError_t e_ = hipGetLastError();                                                         \
+        if (e_ != hipSuccess) return fail(RMHD_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool check_desc(const rmhd_grid_desc* d, std::string& why) {
+    if (!d) { why = "null descriptor"; return false; }
+    if (d->ng != 3) { why = "ng must be 3"; return false; }
+    if (d->active_mask < 1 || d->active_mask > 7 || !(d->active_mask & 1)) {
+        why = "active_mask must include x (bit 0) and lie in 1..7";
+        return false;
+    }
+    for (int k = 0; k < 3; ++k) {
+        const bool act = (d->active_mask >> k) & 1;
+        if (d->n[k] < 1) { why = "n[d] must be >= 1"; return false; }
+        if (act && d->n[k] < 3) { why = "active dimensions need n[d] >= 3"; return false; }
+        if (act && !(d->dx[k] > 0.0)) { why = "dx[d] must be > 0 on active dimensions"; return false; }
+        if (act && d->bc[k] != RMHD_BC_PERIODIC && d->bc[k] != RMHD_BC_COPY) { why = "bad bc"; return false; }
+        if (d->n[k] > (1 << 20)) { why = "n[d] too large"; return false; }
+    }
+    if (d->recon < RMHD_RECON_MINMOD || d->recon > RMHD_RECON_WENO5) { why = "bad recon"; return false; }
+    if (d->precision != RMHD_PREC_FP64 && d->precision != RMHD_PREC_MIXED) { why = "bad precision"; return false; }
+    if (d->precision == RMHD_PREC_MIXED) { why = "mixed precision is not available in this build"; return false; }
+    if (!(d->gamma_ad > 1.0)) { why = "gamma_ad must be > 1"; return false; }
+    if (!(d->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
+    if (!(d->c2p_tol > 0.0) || d->c2p_maxit < 1) { why = "bad recovery tolerance or cap"; return false; }
+    if (d->speed_mode != 0 && d->speed_mode != 1) { why = "bad speed_mode"; return false; }
+    long np = 1;
+    for (int k = 0; k < 3; ++k) np *= d->n[k] + (((d->active_mask >> k) & 1) ? 2 * d->ng : 0);
+    if (np > (1L << 36)) { why = "grid too large"; return false; }
+    return true;
+}
+
+long padded_cells(const rmhd_grid_desc* d) {
+    long np = 1;
+    for (int k = 0; k < 3; ++k) np *= d->n[k] + (((d->active_mask >> k) & 1) ? 2 * d->ng : 0);
+    return np;
+}
+
+size_t ws_layout(const rmhd_grid_desc* d, size_t off[7]) {
+    const size_t Np = (size_t)padded_cells(d);
+    const size_t f14 = up(14 * Np * sizeof(double)), f3 = up(3 * Np * sizeof(double));
+    size_t o = 0;
+    off[0] = o; o += f14;   // rhs
+    off[1] = o; o += f14;   // P1
+    off[2] = o; o += f3;    // R1
+    off[3] = o; o += f14;   // U2
+    off[4] = o; o += f14;   // P2
+    off[5] = o; o += f3;    // R2
+    off[6] = o; o += ALIGN; // counters
+    return o;
+}
+
+long ncells(const Params& p) { return (long)p.n[0] * p.n[1] * p.n[2]; }
+
+enum { T_GHOST = 0, T_FX = 1, T_FY = 2, T_FZ = 3, T_UPD2 = 4, T_UPD3 = 5, T_STAGE1 = 6, T_OTHER = 7 };
+
+// brackets one launch with events when timing is on
+struct Timed {
+    rmhd_ctx* c;
+    int cls;
+    hipEvent_t stop = nullptr;
+    Timed(rmhd_ctx* c_, int cls_) : c(c_), cls(cls_) {
+        if (!c->timing) return;
+        auto& v = c->ev[cls];
+        if (c->used[cls] == v.size()) {
+            hipEvent_t a, b;
+            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+            v.emplace_back(a, b);
+        }
+        auto& pr = v[c->used[cls]++];
+        hipEventRecord(pr.first, c->stream);
+        stop = pr.second;
+    }
+    ~Timed() {
+        if (stop) hipEventRecord(stop, c->stream);
+    }
+};
+unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int ghost_fill(rmhd_ctx* c, double* a, int nf) {
+    const Params& p = c->p;
+    for (int d = 0; d < 3; ++d) {
+        if (!is_active(p, d)) continue;
+        const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+        const long tot = 2L * p.g[d] * p.n[e1] * p.n[e2];
+        Timed t(c, T_GHOST);
+        k_ghost<<<nblk(tot, 256), 256, 0, c->stream>>>(p, a, nf, d);
+        LAUNCH_CHECK();
+    }
+    return RMHD_OK;
+}
+
+template <int RECON, bool CURVED> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
+    const Params& p = c->p;
+    const long waves = (long)((p.n[0] + XSEG - 1) / XSEG) * p.n[1] * p.n[2];
+    {
+        Timed t(c, T_FX);
+        k_flux_x<RECON, CURVED><<<nblk(waves, 4), 256, 0, c->stream>>>(p, P, sig, c->rhs);
+    }
+    LAUNCH_CHECK();
+    const int seglen = 32;
+    if (is_active(p, 1)) {
+        dim3 grid(nblk(p.n[0], 64), p.n[2], nblk(p.n[1], seglen));
+        Timed t(c, T_FY);
+        k_flux_march<1, RECON, CURVED><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
+        LAUNCH_CHECK();
+    }
+    if (is_active(p, 2)) {
+        dim3 grid(nblk(p.n[0], 64), p.n[1], nblk(p.n[2], seglen));
+        Timed t(c, T_FZ);
+        k_flux_march<2, RECON, CURVED><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
+        LAUNCH_CHECK();
+    }
+    return RMHD_OK;
+}
+
+// minus the flux divergence of the (ghost-filled) primitives P into c->rhs
+int flux_div(rmhd_ctx* c, const double* P, const double* sig) {
+    const int r = c->desc.recon;
+    if (c->curved) {
+        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true>(c, P, sig);
+        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true>(c, P, sig);
+        return flux_div_t<REC_WENO5, true>(c, P, sig);
+    }
+    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false>(c, P, sig);
+    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false>(c, P, sig);
+    return flux_div_t<REC_WENO5, false>(c, P, sig);
+}
+
+int stage1(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Pg, double* P1, double* R1,
+           double* U1, int32_t* st) {
+    const long n = ncells(c->p);
+    Timed t(c, T_STAGE1);
+    if (c->curved)
+        k_stage1<true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Pg, P1, R1, U1, st, c->counters);
+    else
+        k_stage1<false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Pg, P1, R1, U1, st, c->counters);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
+template <int STAGE>
+int update(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Us, const double* Ps,
+           const double* R1, const double* R2, double* Uo, double* Po, double* Ro, int32_t* st) {
+    const long n = ncells(c->p);
+    Timed t(c, STAGE == 2 ? T_UPD2 : T_UPD3);
+    if (c->curved)
+        k_update<STAGE, true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                   Ro, st, c->counters);
+    else
+        k_update<STAGE, false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo,
+                                                                    Po, Ro, st, c->counters);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
+int stage2(rmhd_ctx* c, double dt, const double* sig, const double* Un, double* P1, const double* R1, double* U2,
+           double* P2, double* R2, int32_t* st) {
+    int r;
+    if ((r = ghost_fill(c, P1, NF)) != RMHD_OK) return r;
+    if ((r = flux_div(c, P1, sig)) != RMHD_OK) return r;
+    return update<2>(c, dt, sig, Un, nullptr, P1, R1, nullptr, U2, P2, R2, st);
+}
+
+int stage3(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* U2, double* P2,
+           const double* R1, const double* R2, double* Uo, double* Po, int32_t* st) {
+    int r;
+    if ((r = ghost_fill(c, P2, NF)) != RMHD_OK) return r;
+    if ((r = flux_div(c, P2, sig)) != RMHD_OK) return r;
+    return update<3>(c, dt, sig, Un, U2, P2, R1, R2, Uo, Po, nullptr, st);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rmhd_last_error(void) { return g_err.c_str(); }
+
+size_t rmhd_workspace_bytes(const rmhd_grid_desc* desc) {
+    std::string why;
+    if (!check_desc(desc, why)) {
+        g_err = why;
+        return 0;
+    }
+    size_t off[7];
+    return ws_layout(desc, off);
+}
+
+int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes, void* hip_stream, rmhd_ctx** out) {
+    std::string why;
+    if (!out) return fail(RMHD_EINVAL, "out is null");
+    *out = nullptr;
+    if (!check_desc(desc, why)) return fail(RMHD_EINVAL, why);
+    size_t off[7];
+    const size_t need = ws_layout(desc, off);
+    if (!workspace || ws_bytes < need)
+        return fail(RMHD_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
+    if ((reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0) return fail(RMHD_EINVAL, "workspace not 256-byte aligned");
+    rmhd_ctx* c = new rmhd_ctx;
+    c->desc = *desc;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->ws = static_cast<char*>(workspace);
+    c->ws_bytes = ws_bytes;
+    c->rhs = reinterpret_cast<double*>(c->ws + off[0]);
+    c->P1 = reinterpret_cast<double*>(c->ws + off[1]);
+    c->R1 = reinterpret_cast<double*>(c->ws + off[2]);
+    c->U2 = reinterpret_cast<double*>(c->ws + off[3]);
+    c->P2 = reinterpret_cast<double*>(c->ws + off[4]);
+    c->R2 = reinterpret_cast<double*>(c->ws + off[5]);
+    c->counters = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
+    Params& p = c->p;
+    std::memset(&p, 0, sizeof p);
+    for (int d = 0; d < 3; ++d) {
+        p.n[d] = desc->n[d];
+        p.g[d] = ((desc->active_mask >> d) & 1) ? desc->ng : 0;
+        p.np[d] = p.n[d] + 2 * p.g[d];
+        p.bc[d] = desc->bc[d];
+        p.dx[d] = desc->dx[d];
+        p.idx[d] = ((desc->active_mask >> d) & 1) ? 1.0 / desc->dx[d] : 0.0;
+    }
+    p.st[0] = 1;
+    p.st[1] = p.np[0];
+    p.st[2] = (long)p.np[0] * p.np[1];
+    p.Np = (long)p.np[0] * p.np[1] * p.np[2];
+    p.active = desc->active_mask;
+    p.maxit = desc->c2p_maxit;
+    p.speed_mode = desc->speed_mode;
+    p.G = desc->gamma_ad;
+    p.kappa = desc->kappa;
+    p.tol = desc->c2p_tol;
+    c->curved = false;
+    k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete c;
+        return fail(RMHD_EHIP, std::string("init: ") + hipGetErrorString(e));
+    }
+    *out = c;
+    return RMHD_OK;
+}
+
+int rmhd_set_metric(rmhd_ctx* c, const double* alpha, const double* beta, const double* gamma, const double* K) {
+    if (!c) return fail(RMHD_EINVAL, "null context");
+    if ((alpha == nullptr) != (gamma == nullptr)) return fail(RMHD_EINVAL, "alpha and gamma must both be set or both null");
+    if (!alpha && (beta || K)) return fail(RMHD_EINVAL, "beta/K need alpha and gamma");
+    c->p.alp = alpha;
+    c->p.gam = gamma;
+    c->p.bet = beta;
+    c->p.K = K;
+    c->curved = alpha != nullptr;
+    return RMHD_OK;
+}
+
+int rmhd_prim2con(rmhd_ctx* c, const double* P, double* U) {
+    if (!c || !P || !U) return fail(RMHD_EINVAL, "null argument");
+    const long n = ncells(c->p);
+    if (c->curved) k_prim2con<true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, P, U);
+    else k_prim2con<false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, P, U);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
+int rmhd_con2prim(rmhd_ctx* c, const double* U, double* P, int32_t* status) {
+    if (!c || !P || !U) return fail(RMHD_EINVAL, "null argument");
+    const long n = ncells(c->p);
+    if (c->curved) k_con2prim<true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, U, P, status, c->counters);
+    else k_con2prim<false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, U, P, status, c->counters);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
+int rmhd_imex_stage(rmhd_ctx* c, int stage, double dt, const double* sigma, const rmhd_stage_bufs* b) {
+    if (!c || !b || !sigma) return fail(RMHD_EINVAL, "null argument");
+    if (!(dt > 0.0)) return fail(RMHD_EINVAL, "dt must be > 0");
+    if (!b->U_n || !b->P_in || !b->P_out) return fail(RMHD_EINVAL, "U_n, P_in and P_out are required");
+    switch (stage) {
+        case 1:
+            if (!b->R_out) return fail(RMHD_EINVAL, "stage 1 needs R_out");
+            if (b->P_out == b->P_in) return fail(RMHD_EINVAL, "stage 1: P_out must not alias P_in");
+            return stage1(c, dt, sigma, b->U_n, b->P_in, b->P_out, b->R_out, b->U_out, b->status);
+        case 2:
+            if (!b->R1 || !b->U_out || !b->R_out) return fail(RMHD_EINVAL, "stage 2 needs R1, U_out and R_out");
+            if (b->P_out == b->P_in || (const double*)b->U_out == b->U_n)
+                return fail(RMHD_EINVAL, "stage 2 outputs must not alias its inputs");
+            return stage2(c, dt, sigma, b->U_n, b->P_in, b->R1, b->U_out, b->P_out, b->R_out, b->status);
+        case 3:
+            if (!b->U_s || !b->R1 || !b->R2 || !b->U_out) return fail(RMHD_EINVAL, "stage 3 needs U_s, R1, R2, U_out");
+            if (b->P_out == b->P_in) return fail(RMHD_EINVAL, "stage 3: P_out must not alias P_in");
+            return stage3(c, dt, sigma, b->U_n, b->U_s, b->P_in, b->R1, b->R2, b->U_out, b->P_out, b->status);
+        default:
+            return fail(RMHD_EINVAL, "stage must be 1, 2 or 3");
+    }
+}
+
+int rmhd_step(rmhd_ctx* c, double dt, const double* sigma, double* U, double* P) {
+    if (!c || !sigma || !U || !P) return fail(RMHD_EINVAL, "null argument");
+    if (!(dt > 0.0)) return fail(RMHD_EINVAL, "dt must be > 0");
+    int r;
+    if ((r = stage1(c, dt, sigma, U, P, c->P1, c->R1, nullptr, nullptr)) != RMHD_OK) return r;
+    if ((r = stage2(c, dt, sigma, U, c->P1, c->R1, c->U2, c->P2, c->R2, nullptr)) != RMHD_OK) return r;
+    return stage3(c, dt, sigma, U, c->U2, c->P2, c->R1, c->R2, U, P, nullptr);
+}
+
+int rmhd_max_signal_speed(rmhd_ctx* c, double* host_out) {
+    if (!c || !host_out) return fail(RMHD_EINVAL, "null argument");
+    k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters + 1, 1);
+    LAUNCH_CHECK();
+    const long n = ncells(c->p);
+    const unsigned blocks = (unsigned)std::min<long>(nblk(n, 256), 4096);
+    if (c->curved) k_max_speed<true><<<blocks, 256, 0, c->stream>>>(c->p, c->counters + 1);
+    else k_max_speed<false><<<blocks, 256, 0, c->stream>>>(c->p, c->counters + 1);
+    LAUNCH_CHECK();
+    unsigned long long bits = 0;
+    HIP_TRY(hipMemcpyAsync(&bits, c->counters + 1, sizeof bits, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    double v;
+    std::memcpy(&v, &bits, sizeof v);
+    *host_out = v;
+    return RMHD_OK;
+}
+
+int rmhd_failures(rmhd_ctx* c, int64_t* host_out) {
+    if (!c || !host_out) return fail(RMHD_EINVAL, "null argument");
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, c->counters, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 1);
+    LAUNCH_CHECK();
+    *host_out = (int64_t)n;
+    return RMHD_OK;
+}
+
+int rmhd_timing(rmhd_ctx* c, int enable) {
+    if (!c) return fail(RMHD_EINVAL, "null context");
+    c->timing = enable != 0;
+    return RMHD_OK;
+}
+
+int rmhd_timing_read(rmhd_ctx* c, double* ms_out, int64_t* launches_out) {
+    if (!c || !ms_out || !launches_out) return fail(RMHD_EINVAL, "null argument");
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int k = 0; k < RMHD_TIMING_CLASSES; ++k) {
+        double tot = 0.0;
+        for (size_t i = 0; i < c->used[k]; ++i) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, c->ev[k][i].first, c->ev[k][i].second));
+            tot += ms;
+        }
+        ms_out[k] = tot;
+        launches_out[k] = (int64_t)c->used[k];
+        c->used[k] = 0;
+    }
+    return RMHD_OK;
+}
+
+int rmhd_destroy(rmhd_ctx* c) {
+    if (!c) return RMHD_OK;
+    for (auto& v : c->ev)
+        for (auto& pr : v) {
+            hipEventDestroy(pr.first);
+            hipEventDestroy(pr.second);
+        }
+    delete c;
+    return RMHD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,560 @@
+// gfx950 kernels of the IMEX-SSP2(2,2,2) stage of resistive GRMHD.
+//
+// Data: float64 SoA over the padded grid (x fastest), one field per plane.
+// The flux divergence is split by direction:
+//   x: one wave64 per row segment of 62 cells; every lane reconstructs its
+//      own cell to both faces (shared WENO smoothness indicators), the right
+//      neighbour's left-face state and the left neighbour's face flux arrive
+//      by cross-lane shuffles, so each face flux is computed once;
+//   y, z: lanes run along x (coalesced loads) and each lane marches along the
+//      flux direction, carrying the previous face state and flux in
+//      registers.
+// The pointwise kernels add the non-stiff sources, assemble the IMEX stage
+// and run the stiff recovery, one cell per lane.
+#pragma once
+#include "rmhd_phys.hpp"
+
+namespace rmhd {
+
+struct Params {
+    int n[3], g[3], np[3], active, bc[3], maxit, speed_mode;
+    long st[3], Np;
+    double dx[3], idx[3], G, kappa, tol;
+    // metric (nullptr alp/gam: flat), beta/K may be nullptr
+    const double* alp;
+    const double* bet;
+    const double* gam;
+    const double* K;
+};
+
+__host__ __device__ __forceinline__ bool is_active(const Params& p, int d) { return (p.active >> d) & 1; }
+
+// padded index along d of the interior cell that a ghost index maps to
+__device__ __forceinline__ int bc_map(const Params& p, int d, int c) {
+    const int g = p.g[d], n = p.n[d];
+    if (c >= g && c < g + n) return c;
+    if (p.bc[d] == 0) return c < g ? c + n : c - n;
+    return c < g ? g : g + n - 1;
+}
+
+template <class R> __device__ __forceinline__ void load_geo(const Params& p, long o, Geo<R>& m) {
+    m.alp = R(p.alp[o]);
+    for (int a = 0; a < 3; ++a) m.bet[a] = p.bet ? R(p.bet[a * p.Np + o]) : R(0);
+    for (int a = 0; a < 6; ++a) m.g[a] = R(p.gam[a * p.Np + o]);
+    geo_finish(m);
+}
+
+// metric at the face between o and o + s (4th-order interpolation)
+template <class R> __device__ __forceinline__ void face_geo(const Params& p, long o, long s, Geo<R>& m) {
+    auto I4 = [&](const double* f) {
+        return (-f[o - s] + 9.0 * f[o] + 9.0 * f[o + s] - f[o + 2 * s]) * 0.0625;
+    };
+    m.alp = R(I4(p.alp));
+    for (int a = 0; a < 3; ++a) m.bet[a] = p.bet ? R(I4(p.bet + a * p.Np)) : R(0);
+    for (int a = 0; a < 6; ++a) m.g[a] = R(I4(p.gam + a * p.Np));
+    geo_finish(m);
+}
+
+template <int D, class R> __device__ __forceinline__ void speeds(const Params& p, const Geo<R>& m, R& lp, R& lm) {
+    const R s = sqrt(m.gi[sidx(D, D)]);
+    if (p.speed_mode == 0) {
+        const R b = m.bet[D] / m.alp;
+        lp = s - b;
+        lm = -s - b;
+    } else {
+        lp = m.alp * s - m.bet[D];
+        lm = -m.alp * s - m.bet[D];
+    }
+    lp = fmax(lp, R(0));
+    lm = fmin(lm, R(0));
+}
+
+// a face state is unusable if rho <= 0, p <= 0 or v^2 >= 1
+template <class R> __device__ __forceinline__ bool bad_state(const Geo<R>& m, const R* P) {
+    R vl[3];
+    lower(m.g, P + I_V, vl);
+    const R v2 = dot3(vl, P + I_V);
+    return !(P[I_RHO] > R(0)) || !(P[I_P] > R(0)) || !(v2 < R(1));
+}
+
+// HLLE flux of direction D at a face with metric m (Sec. III)
+template <int D, class R>
+__device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, const R* PL, const R* PR, R Jd, R* Fh) {
+    R lp, lm;
+    speeds<D>(p, m, lp, lm);
+    const R id = R(1) / (lp - lm);
+    const R cL = lp * id, cR = -lm * id, cU = lp * lm * id;
+    const R G = R(p.G);
+    R U[NF], F[NF];
+    prim2con(m, G, PL, U);
+    phys_flux<D>(m, G, PL, U, Jd, F);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) Fh[a] = cL * F[a] - cU * U[a];
+    prim2con(m, G, PR, U);
+    phys_flux<D>(m, G, PR, U, Jd, F);
+#pragma unroll
+    for (int a = 0; a < NF; ++a) Fh[a] += cR * F[a] + cU * U[a];
+}
+
+// ------------------------------------------------------------------ x fluxes
+constexpr int XSEG = 62;
+
+template <int RECON, bool CURVED>
+__global__ __launch_bounds__(256) void k_flux_x(const Params p, const double* __restrict__ P,
+                                                const double* __restrict__ sig, double* __restrict__ rhs) {
+    const int lane = threadIdx.x & 63;
+    const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int nseg = (p.n[0] + XSEG - 1) / XSEG;
+    const long nrows = (long)p.n[1] * p.n[2];
+    if (wid >= nrows * nseg) return;
+    const int seg = (int)(wid % nseg);
+    const long row = wid / nseg;
+    const int j = (int)(row % p.n[1]) + p.g[1];
+    const int k = (int)(row / p.n[1]) + p.g[2];
+    const int ilast = p.g[0] + p.n[0];                 // right ghost next to the last cell
+    const int i = p.g[0] - 1 + seg * XSEG + lane;     // this lane's cell (padded index)
+    const int ic = i <= ilast ? i : ilast;
+    const long o = ((long)k * p.np[1] + j) * p.np[0] + ic;
+    const long Np = p.Np;
+
+    double fm[NF], fp[NF], Pc[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const double* a = P + f * Np + o;
+        const double s[5] = {a[-2], a[-1], a[0], a[1], a[2]};
+        recon<RECON>(s, fm[f], fp[f]);
+        Pc[f] = s[2];
+    }
+    // cell-centre current, x component (charge flux at faces = mean of the two cells)
+    Geo<double> mc;
+    if (CURVED) {
+        mc.alp = 1.0;
+        mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
+        for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
+        geo_finish(mc);
+    } else {
+        geo_flat(mc);
+    }
+    const long os = o - ic + bc_map(p, 0, ic);
+    double J[3];
+    current(mc, Pc, sig[os], J);
+    const double JR = __shfl_down(J[0], 1);
+    double PR[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) PR[f] = __shfl_down(fm[f], 1);
+
+    // face i + 1/2
+    Geo<double> m;
+    if (CURVED) face_geo(p, o, 1, m); else geo_flat(m);
+    if (bad_state(m, fp))
+        for (int f = 0; f < NF; ++f) fp[f] = Pc[f];
+    if (bad_state(m, PR))
+        for (int f = 0; f < NF; ++f) PR[f] = P[f * Np + o + 1];
+    double Fh[NF];
+    face_flux<0>(p, m, fp, PR, 0.5 * (J[0] + JR), Fh);
+
+    const bool cell = lane >= 1 && lane <= XSEG && i >= p.g[0] && i < ilast;
+    const double ih = p.idx[0];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const double Fl = __shfl_up(Fh[f], 1);
+        if (cell) rhs[f * Np + o] = -(Fh[f] - Fl) * ih;
+    }
+}
+
+// -------------------------------------------------------------- y / z fluxes
+template <int D, int RECON, bool CURVED>
+__global__ __launch_bounds__(64) void k_flux_march(const Params p, const double* __restrict__ P,
+                                                   const double* __restrict__ sig, double* __restrict__ rhs,
+                                                   int seglen) {
+    const int i = blockIdx.x * 64 + threadIdx.x;
+    if (i >= p.n[0]) return;
+    constexpr int E = (D == 1) ? 2 : 1;               // the other transverse dimension
+    const int e = blockIdx.y + p.g[E];
+    const int c0 = blockIdx.z * seglen;               // first cell (interior index) of the segment
+    const int c1 = min(c0 + seglen, p.n[D]);
+    const long s = p.st[D];
+    const long Np = p.Np;
+    const long base = (long)(i + p.g[0]) + (long)e * p.st[E];
+    const double ih = p.idx[D];
+
+    double PLc[NF], Fprev[NF], Jprev = 0.0;
+    for (int c = c0 - 1; c <= c1; ++c) {
+        const int cp = c + p.g[D];
+        const long o = base + (long)cp * s;
+        double fm[NF], fp[NF], Pc[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            const double* a = P + f * Np + o;
+            const double st5[5] = {a[-2 * s], a[-s], a[0], a[s], a[2 * s]};
+            recon<RECON>(st5, fm[f], fp[f]);
+            Pc[f] = st5[2];
+        }
+        Geo<double> mc;
+        if (CURVED) {
+            mc.alp = 1.0;
+            mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
+            for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
+            geo_finish(mc);
+        } else {
+            geo_flat(mc);
+        }
+        const long os = o + (long)(bc_map(p, D, cp) - cp) * s;
+        double J[3];
+        current(mc, Pc, sig[os], J);
+        if (c >= c0) {
+            // face between c - 1 and c
+            Geo<double> m;
+            if (CURVED) face_geo(p, o - s, s, m); else geo_flat(m);
+            if (bad_state(m, PLc))
+                for (int f = 0; f < NF; ++f) PLc[f] = P[f * Np + o - s];
+            if (bad_state(m, fm))
+                for (int f = 0; f < NF; ++f) fm[f] = Pc[f];
+            double Fh[NF];
+            face_flux<D>(p, m, PLc, fm, 0.5 * (Jprev + J[D]), Fh);
+            if (c > c0) {
+                const long oc = o - s;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) rhs[f * Np + oc] -= (Fh[f] - Fprev[f]) * ih;
+            }
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Fprev[f] = Fh[f];
+        }
+#pragma unroll
+        for (int f = 0; f < NF; ++f) PLc[f] = fp[f];
+        Jprev = J[D];
+    }
+}
+
+// ---------------------------------------------------------------- ghost fill
+// faces only: ghost layers along each active d, interior extents elsewhere
+__global__ void k_ghost(const Params p, double* __restrict__ a, int nf, int d) {
+    const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+    const long n1 = p.n[e1], n2 = p.n[e2];
+    const long tot = 2L * p.g[d] * n1 * n2;
+    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= tot) return;
+    const int a1 = (int)(t % n1) + p.g[e1];
+    t /= n1;
+    const int a2 = (int)(t % n2) + p.g[e2];
+    t /= n2;
+    const int layer = (int)t;   // 0..2g-1
+    const int c = layer < p.g[d] ? layer : p.n[d] + layer;
+    const int src = bc_map(p, d, c);
+    const long ob = (long)a1 * p.st[e1] + (long)a2 * p.st[e2];
+    const long od = ob + (long)c * p.st[d], os = ob + (long)src * p.st[d];
+    for (int f = 0; f < nf; ++f) a[f * p.Np + od] = a[f * p.Np + os];
+}
+
+// ------------------------------------------------------------- interior map
+__device__ __forceinline__ bool interior_cell(const Params& p, long t, long& o) {
+    const long n0 = p.n[0], n1 = p.n[1];
+    if (t >= n0 * n1 * p.n[2]) return false;
+    const int i = (int)(t % n0) + p.g[0];
+    const int j = (int)((t / n0) % n1) + p.g[1];
+    const int k = (int)(t / (n0 * n1)) + p.g[2];
+    o = ((long)k * p.np[1] + j) * p.np[0] + i;
+    return true;
+}
+
+template <bool CURVED> __device__ __forceinline__ void cell_geo(const Params& p, long o, Geo<double>& m) {
+    if (CURVED) load_geo(p, o, m); else geo_flat(m);
+}
+
+template <bool CURVED>
+__global__ __launch_bounds__(256) void k_prim2con(const Params p, const double* __restrict__ P,
+                                                  double* __restrict__ U) {
+    long o;
+    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    Geo<double> m;
+    cell_geo<CURVED>(p, o, m);
+    double Pc[NF], Uc[NF];
+    for (int f = 0; f < NF; ++f) Pc[f] = P[f * p.Np + o];
+    prim2con(m, p.G, Pc, Uc);
+    for (int f = 0; f < NF; ++f) U[f * p.Np + o] = Uc[f];
+}
+
+__device__ __forceinline__ void rec_setup(const Params& p, const Geo<double>& m, const double* U, RecIn& k) {
+    k.G = p.G;
+    k.D = U[I_D];
+    k.tau = U[I_TAU];
+    for (int i = 0; i < 3; ++i) {
+        k.S[i] = U[I_S + i];
+        k.Bc[i] = U[I_B + i];
+    }
+    for (int a = 0; a < 6; ++a) { k.g[a] = m.g[a]; k.gi[a] = m.gi[a]; }
+    k.sg = m.sg;
+    k.isg = m.isg;
+    lower(m.g, k.Bc, k.Bl);
+    for (int i = 0; i < 3; ++i) k.Bl[i] *= m.isg;     // undensitised, lowered B
+}
+
+__device__ __forceinline__ void write_prims(const Params& p, long o, const Geo<double>& m, const double* U,
+                                            const double* x, const double* Ec, double* P) {
+    const double* v = x + 1;
+    double vl[3];
+    lower(m.g, v, vl);
+    const double W = 1.0 / sqrt(1.0 - dot3(vl, v));
+    P[I_RHO * p.Np + o] = U[I_D] * m.isg / W;
+    P[I_P * p.Np + o] = x[0];
+    for (int i = 0; i < 3; ++i) {
+        P[(I_V + i) * p.Np + o] = v[i];
+        P[(I_B + i) * p.Np + o] = U[I_B + i] * m.isg;
+        P[(I_E + i) * p.Np + o] = Ec[i] * m.isg;
+    }
+    for (int f = I_PHI; f < NF; ++f) P[f * p.Np + o] = U[f] * m.isg;
+}
+
+__device__ __forceinline__ void copy_prims(const Params& p, long o, const double* Pg, double* P) {
+    for (int f = 0; f < NF; ++f) P[f * p.Np + o] = Pg[f];
+}
+
+// plain recovery (E fixed)
+template <bool CURVED>
+__global__ __launch_bounds__(256) void k_con2prim(const Params p, const double* __restrict__ U,
+                                                  double* __restrict__ P, int* __restrict__ status,
+                                                  unsigned long long* nfail) {
+    long o;
+    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    Geo<double> m;
+    cell_geo<CURVED>(p, o, m);
+    double Uc[NF], Pg[NF];
+    for (int f = 0; f < NF; ++f) { Uc[f] = U[f * p.Np + o]; Pg[f] = P[f * p.Np + o]; }
+    RecIn k;
+    rec_setup(p, m, Uc, k);
+    double x[4] = {Pg[I_P], Pg[I_V], Pg[I_V + 1], Pg[I_V + 2]};
+    int it;
+    const double Ec[3] = {Uc[I_E], Uc[I_E + 1], Uc[I_E + 2]};
+    const int st = recover_plain(k, Ec, x, p.tol, p.maxit, &it);
+    if (st >= 0) write_prims(p, o, m, Uc, x, Ec, P);
+    else atomicAdd(nfail, 1ull);
+    if (status) status[o] = st;
+}
+
+// ------------------------------------------------------- explicit sources
+// eq. GRRMHD_flux_form at a cell centre, E rows without R_E; metric
+// derivatives by 4th-order central differences along active dimensions
+template <bool CURVED>
+__device__ __forceinline__ void sources(const Params& p, long o, const Geo<double>& m, const double* Pc,
+                                        const double* Uc, double* S) {
+    const double* v = Pc + I_V;
+    if (!CURVED) {
+        for (int f = 0; f < NF; ++f) S[f] = 0.0;
+        for (int i = 0; i < 3; ++i) S[I_E + i] = -Uc[I_Q] * v[i];
+        S[I_PHI] = -p.kappa * Uc[I_PHI];
+        S[I_PSI] = Uc[I_Q] - p.kappa * Uc[I_PSI];
+        return;
+    }
+    double da[3] = {0, 0, 0}, db[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, dg[3][6];
+    for (int d = 0; d < 3; ++d)
+        for (int a = 0; a < 6; ++a) dg[d][a] = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (!is_active(p, d)) continue;
+        const long s = p.st[d];
+        const double c = p.idx[d] / 12.0;
+        auto D4 = [&](const double* f) { return (f[o - 2 * s] - 8.0 * f[o - s] + 8.0 * f[o + s] - f[o + 2 * s]) * c; };
+        da[d] = D4(p.alp);
+        if (p.bet)
+            for (int a = 0; a < 3; ++a) db[d][a] = D4(p.bet + a * p.Np);
+        for (int a = 0; a < 6; ++a) dg[d][a] = D4(p.gam + a * p.Np);
+    }
+    const double a = m.alp;
+    // Gamma^i = gamma^il (gamma^jk d_j gamma_lk - 1/2 gamma^jk d_l gamma_jk)
+    double A[3], Gm[3], gda[3];
+    for (int l = 0; l < 3; ++l) {
+        double s1 = 0.0, s2 = 0.0;
+        for (int j = 0; j < 3; ++j)
+            for (int kk = 0; kk < 3; ++kk) {
+                s1 += m.gi[sidx(j, kk)] * dg[j][sidx(l, kk)];
+                s2 += m.gi[sidx(j, kk)] * dg[l][sidx(j, kk)];
+            }
+        A[l] = s1 - 0.5 * s2;
+    }
+    for (int i = 0; i < 3; ++i) {
+        Gm[i] = m.gi[sidx(i, 0)] * A[0] + m.gi[sidx(i, 1)] * A[1] + m.gi[sidx(i, 2)] * A[2];
+        gda[i] = m.gi[sidx(i, 0)] * da[0] + m.gi[sidx(i, 1)] * da[1] + m.gi[sidx(i, 2)] * da[2];
+    }
+    // densitised stress with both indices up
+    const double* B = Pc + I_B;
+    const double* E = Pc + I_E;
+    double vl[3], Bl[3], El[3];
+    lower(m.g, v, vl);
+    lower(m.g, B, Bl);
+    lower(m.g, E, El);
+    const double W2 = 1.0 / (1.0 - dot3(vl, v));
+    const double hW2 = (Pc[I_RHO] + p.G / (p.G - 1.0) * Pc[I_P]) * W2;
+    const double pt = Pc[I_P] + 0.5 * (dot3(El, E) + dot3(Bl, B));
+    double Su[6];
+    for (int j = 0; j < 3; ++j)
+        for (int kk = j; kk < 3; ++kk)
+            Su[sidx(j, kk)] = m.sg * (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk] + m.gi[sidx(j, kk)] * pt);
+    const double* Sl = Uc + I_S;
+    double Sup[3];
+    for (int i = 0; i < 3; ++i) Sup[i] = m.gi[sidx(i, 0)] * Sl[0] + m.gi[sidx(i, 1)] * Sl[1] + m.gi[sidx(i, 2)] * Sl[2];
+    double Ktr = 0.0, SK = 0.0;
+    if (p.K) {
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                const double kij = p.K[sidx(i, j) * p.Np + o];
+                Ktr += m.gi[sidx(i, j)] * kij;
+                SK += Su[sidx(i, j)] * kij;
+            }
+    }
+    S[I_D] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        double t = 0.0;
+        for (int j = 0; j < 3; ++j)
+            for (int kk = 0; kk < 3; ++kk) t += Su[sidx(j, kk)] * dg[i][sidx(j, kk)];
+        S[I_S + i] = 0.5 * a * t + (Sl[0] * db[i][0] + Sl[1] * db[i][1] + Sl[2] * db[i][2]) -
+                     (Uc[I_TAU] + Uc[I_D]) * da[i];
+    }
+    S[I_TAU] = a * SK - dot3(Sup, da);
+    for (int i = 0; i < 3; ++i) {
+        const double bb = Uc[I_B] * db[0][i] + Uc[I_B + 1] * db[1][i] + Uc[I_B + 2] * db[2][i];
+        const double eb = Uc[I_E] * db[0][i] + Uc[I_E + 1] * db[1][i] + Uc[I_E + 2] * db[2][i];
+        S[I_B + i] = -bb + Uc[I_PHI] * (gda[i] - a * Gm[i]);
+        S[I_E + i] = -eb + Uc[I_PSI] * (gda[i] - a * Gm[i]) - a * Uc[I_Q] * v[i];
+    }
+    S[I_PHI] = -a * Uc[I_PHI] * Ktr + dot3(Uc + I_B, da) - a * p.kappa * Uc[I_PHI];
+    S[I_PSI] = -a * Uc[I_PSI] * Ktr + dot3(Uc + I_E, da) + a * Uc[I_Q] - a * p.kappa * Uc[I_PSI];
+    S[I_Q] = 0.0;
+}
+
+// --------------------------------------------------------------- stages
+// gamma of table imex
+__host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560; }
+
+// stage 1: E(1) = E^n + gamma dt R_E(U(1)), everything else unchanged
+template <bool CURVED>
+__global__ __launch_bounds__(256) void k_stage1(const Params p, double dt, const double* __restrict__ sig,
+                                                const double* __restrict__ Un, const double* __restrict__ Pg_,
+                                                double* __restrict__ P1, double* __restrict__ R1,
+                                                double* __restrict__ U1, int* __restrict__ status,
+                                                unsigned long long* nfail) {
+    long o;
+    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    Geo<double> m;
+    cell_geo<CURVED>(p, o, m);
+    double Uc[NF];
+    for (int f = 0; f < NF; ++f) Uc[f] = Un[f * p.Np + o];
+    RecIn k;
+    rec_setup(p, m, Uc, k);
+    const double gdt = GAM_IMEX() * dt;
+    for (int i = 0; i < 3; ++i) k.Es[i] = Uc[I_E + i];
+    k.cfac = gdt * m.alp * sig[o];
+    double x[4] = {Pg_[I_P * p.Np + o], Pg_[I_V * p.Np + o], Pg_[(I_V + 1) * p.Np + o], Pg_[(I_V + 2) * p.Np + o]};
+    double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
+    int it, st;
+    if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
+    else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
+    if (st >= 0) {
+        write_prims(p, o, m, Uc, x, E, P1);
+    } else {
+        for (int f = 0; f < NF; ++f) P1[f * p.Np + o] = Pg_[f * p.Np + o];
+        for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
+        atomicAdd(nfail, 1ull);
+    }
+    for (int i = 0; i < 3; ++i) R1[i * p.Np + o] = (E[i] - k.Es[i]) / gdt;
+    if (U1) {
+        for (int f = 0; f < NF; ++f) U1[f * p.Np + o] = Uc[f];
+        for (int i = 0; i < 3; ++i) U1[(I_E + i) * p.Np + o] = E[i];
+    }
+    if (status) status[o] = st;
+}
+
+// stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
+// divergence of P_s has been accumulated into rhs
+template <int STAGE, bool CURVED>
+__global__ __launch_bounds__(256) void k_update(const Params p, double dt, const double* __restrict__ sig,
+                                                const double* __restrict__ Un, const double* __restrict__ Us,
+                                                const double* __restrict__ Ps, const double* __restrict__ R1,
+                                                const double* __restrict__ R2, const double* __restrict__ rhs,
+                                                double* __restrict__ Uo, double* __restrict__ Po,
+                                                double* __restrict__ Ro, int* __restrict__ status,
+                                                unsigned long long* nfail) {
+    long o;
+    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    const long Np = p.Np;
+    Geo<double> m;
+    cell_geo<CURVED>(p, o, m);
+    double Pc[NF], L[NF];
+    {
+        double Uc[NF], S[NF];
+        for (int f = 0; f < NF; ++f) Pc[f] = Ps[f * Np + o];
+        prim2con(m, p.G, Pc, Uc);
+        sources<CURVED>(p, o, m, Pc, Uc, S);
+        for (int f = 0; f < NF; ++f) L[f] = rhs[f * Np + o] + S[f];
+    }
+    const double g = GAM_IMEX();
+    double Y[NF];
+    if (STAGE == 2) {
+        for (int f = 0; f < NF; ++f) Y[f] = Un[f * Np + o] + dt * L[f];
+        double Es[3];
+        for (int i = 0; i < 3; ++i) Es[i] = Y[I_E + i] + dt * (1.0 - 2.0 * g) * R1[i * Np + o];
+        RecIn k;
+        rec_setup(p, m, Y, k);
+        for (int i = 0; i < 3; ++i) k.Es[i] = Es[i];
+        k.cfac = g * dt * m.alp * sig[o];
+        double x[4] = {Pc[I_P], Pc[I_V], Pc[I_V + 1], Pc[I_V + 2]};
+        double E[3] = {Es[0], Es[1], Es[2]};
+        int it, st;
+        if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
+        else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
+        if (st >= 0) {
+            write_prims(p, o, m, Y, x, E, Po);
+        } else {
+            copy_prims(p, o, Pc, Po);
+            for (int i = 0; i < 3; ++i) E[i] = Es[i];
+            atomicAdd(nfail, 1ull);
+        }
+        for (int f = 0; f < NF; ++f) Uo[f * Np + o] = (f >= I_E && f < I_E + 3) ? E[f - I_E] : Y[f];
+        for (int i = 0; i < 3; ++i) Ro[i * Np + o] = (E[i] - Es[i]) / (g * dt);
+        if (status) status[o] = st;
+    } else {
+        // U^{n+1} = (U^n + U(2))/2 + dt/2 F(U(2)) + dt/2 (2 gamma R1 + (1 - gamma) R2) on E
+        for (int f = 0; f < NF; ++f) Y[f] = 0.5 * (Un[f * Np + o] + Us[f * Np + o]) + 0.5 * dt * L[f];
+        for (int i = 0; i < 3; ++i)
+            Y[I_E + i] += 0.5 * dt * (2.0 * g * R1[i * Np + o] + (1.0 - g) * R2[i * Np + o]);
+        RecIn k;
+        rec_setup(p, m, Y, k);
+        double x[4] = {Pc[I_P], Pc[I_V], Pc[I_V + 1], Pc[I_V + 2]};
+        const double E[3] = {Y[I_E], Y[I_E + 1], Y[I_E + 2]};
+        int it;
+        const int st = recover_plain(k, E, x, p.tol, p.maxit, &it);
+        for (int f = 0; f < NF; ++f) Uo[f * Np + o] = Y[f];
+        if (st >= 0) {
+            write_prims(p, o, m, Y, x, E, Po);
+        } else {
+            copy_prims(p, o, Pc, Po);
+            atomicAdd(nfail, 1ull);
+        }
+        if (status) status[o] = st;
+    }
+}
+
+// ---------------------------------------------------- max signal speed (CFL)
+template <bool CURVED>
+__global__ __launch_bounds__(256) void k_max_speed(const Params p, unsigned long long* out) {
+    long o;
+    double best = 0.0;
+    const long ncell = (long)p.n[0] * p.n[1] * p.n[2];
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < ncell; t += (long)gridDim.x * blockDim.x) {
+        interior_cell(p, t, o);
+        Geo<double> m;
+        cell_geo<CURVED>(p, o, m);
+        double lp, lm;
+        if (is_active(p, 0)) { speeds<0>(p, m, lp, lm); best = fmax(best, fmax(lp, -lm) * p.idx[0]); }
+        if (is_active(p, 1)) { speeds<1>(p, m, lp, lm); best = fmax(best, fmax(lp, -lm) * p.idx[1]); }
+        if (is_active(p, 2)) { speeds<2>(p, m, lp, lm); best = fmax(best, fmax(lp, -lm) * p.idx[2]); }
+    }
+    // wavefront reduction, then one atomic per wave on the ordered bit pattern
+    for (int off = 32; off > 0; off >>= 1) best = fmax(best, __shfl_xor(best, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ void k_zero_u64(unsigned long long* a, int n) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < n) a[t] = 0ull;
+}
+
+}  // namespace rmhd

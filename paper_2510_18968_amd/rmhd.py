@@ -1,0 +1,222 @@
+"""Python binding of the C ABI in include/rmhd.h (argument marshalling only).
+
+Every step of the stage update runs in the gfx950 kernels of
+``librmhd.so``; this module only passes device pointers of torch tensors and
+the current HIP stream.  It raises if the library is missing or if the
+tensors are not float64 CUDA (HIP) tensors of the padded grid shape.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librmhd.so")
+
+RECON = {"minmod": 0, "mc2": 1, "weno5": 2}
+BC = {"periodic": 0, "copy": 1}
+PREC = {"fp64": 0, "mixed": 1}
+
+SYMBOLS = ("rmhd_workspace_bytes", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
+           "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
+           "rmhd_last_error", "rmhd_timing", "rmhd_timing_read")
+TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("active_mask", C.c_int32), ("ng", C.c_int32), ("bc", C.c_int32 * 3),
+                ("recon", C.c_int32), ("precision", C.c_int32), ("c2p_maxit", C.c_int32),
+                ("speed_mode", C.c_int32), ("x0", C.c_double * 3), ("dx", C.c_double * 3),
+                ("gamma_ad", C.c_double), ("kappa", C.c_double), ("c2p_tol", C.c_double)]
+
+
+class StageBufs(C.Structure):
+    _fields_ = [("U_n", C.c_void_p), ("U_s", C.c_void_p), ("P_in", C.c_void_p), ("R1", C.c_void_p),
+                ("R2", C.c_void_p), ("U_out", C.c_void_p), ("P_out", C.c_void_p), ("R_out", C.c_void_p),
+                ("status", C.c_void_p)]
+
+
+class RMHDError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load the in-tree gfx950 library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RMHDError(f"{LIB_PATH} is missing: build it with paper_2510_18968_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, gp = C.c_void_p, C.POINTER(GridDesc)
+        sig = {
+            "rmhd_workspace_bytes": (C.c_size_t, [gp]),
+            "rmhd_init_grid": (C.c_int, [gp, vp, C.c_size_t, vp, C.POINTER(vp)]),
+            "rmhd_set_metric": (C.c_int, [vp, vp, vp, vp, vp]),
+            "rmhd_prim2con": (C.c_int, [vp, vp, vp]),
+            "rmhd_con2prim": (C.c_int, [vp, vp, vp, vp]),
+            "rmhd_imex_stage": (C.c_int, [vp, C.c_int, C.c_double, vp, C.POINTER(StageBufs)]),
+            "rmhd_step": (C.c_int, [vp, C.c_double, vp, vp, vp]),
+            "rmhd_max_signal_speed": (C.c_int, [vp, C.POINTER(C.c_double)]),
+            "rmhd_failures": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+            "rmhd_destroy": (C.c_int, [vp]),
+            "rmhd_last_error": (C.c_char_p, []),
+            "rmhd_timing": (C.c_int, [vp, C.c_int]),
+            "rmhd_timing_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RMHDError(f"{what} failed ({rc}): {lib().rmhd_last_error().decode()}")
+
+
+def make_desc(n, active, dx, bc, gamma_ad, recon="weno5", x0=(0.0, 0.0, 0.0), kappa=1.0, precision="fp64",
+              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0) -> GridDesc:
+    d = GridDesc()
+    for k in range(3):
+        d.n[k] = int(n[k])
+        d.bc[k] = int(bc[k]) if not isinstance(bc[k], str) else BC[bc[k]]
+        d.x0[k] = float(x0[k])
+        d.dx[k] = float(dx[k])
+    d.active_mask, d.ng = int(active), 3
+    d.recon = RECON[recon] if isinstance(recon, str) else int(recon)
+    d.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    d.c2p_maxit, d.speed_mode = int(c2p_maxit), int(speed_mode)
+    d.gamma_ad, d.kappa, d.c2p_tol = float(gamma_ad), float(kappa), float(c2p_tol)
+    return d
+
+
+class Grid:
+    """A context of the C library plus its workspace (a torch uint8 tensor)."""
+
+    def __init__(self, desc: GridDesc, device="cuda"):
+        self.desc = desc
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RMHDError("the library runs on a HIP device only")
+        nbytes = lib().rmhd_workspace_bytes(C.byref(desc))
+        if nbytes == 0:
+            raise RMHDError(f"invalid grid: {lib().rmhd_last_error().decode()}")
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self._ws_ptr = (base + 255) // 256 * 256
+        self._ctx = C.c_void_p()
+        self._keep = []
+        _check(lib().rmhd_init_grid(C.byref(desc), C.c_void_p(self._ws_ptr), nbytes, self._stream(),
+                                    C.byref(self._ctx)), "rmhd_init_grid")
+        g = [3 if (desc.active_mask >> k) & 1 else 0 for k in range(3)]
+        self.padded = (desc.n[2] + 2 * g[2], desc.n[1] + 2 * g[1], desc.n[0] + 2 * g[0])
+        self.ghosts = tuple(g)
+
+    def _stream(self):
+        return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def _ptr(self, t, nf=None, dtype=torch.float64):
+        if t is None:
+            return None
+        if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+            raise RMHDError("expected a contiguous device tensor of dtype %s" % dtype)
+        shape = self.padded if nf is None else (nf,) + self.padded
+        if tuple(t.shape) != shape:
+            raise RMHDError(f"expected shape {shape}, got {tuple(t.shape)}")
+        return C.c_void_p(t.data_ptr())
+
+    def empty(self, nf=14):
+        return torch.zeros((nf,) + self.padded, dtype=torch.float64, device=self.device)
+
+    def set_metric(self, metric=None):
+        """metric: [16, ...] tensor (alpha, beta^i, gamma_ij, K_ij) or None for flat space."""
+        if metric is None:
+            _check(lib().rmhd_set_metric(self._ctx, None, None, None, None), "rmhd_set_metric")
+            self._keep = []
+            return
+        self._ptr(metric, 16)
+        a, b, g, k = metric[0], metric[1:4], metric[4:10], metric[10:16]
+        self._keep = [metric]
+        _check(lib().rmhd_set_metric(self._ctx, C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()),
+                                     C.c_void_p(g.data_ptr()), C.c_void_p(k.data_ptr())), "rmhd_set_metric")
+
+    def set_metric_fields(self, alpha, beta, gamma, K):
+        ptr = lambda t, nf: None if t is None else self._ptr(t, nf)
+        self._keep = [alpha, beta, gamma, K]
+        _check(lib().rmhd_set_metric(self._ctx, ptr(alpha, None), ptr(beta, 3), ptr(gamma, 6), ptr(K, 6)),
+               "rmhd_set_metric")
+
+    def prim2con(self, P, U=None):
+        U = self.empty() if U is None else U
+        _check(lib().rmhd_prim2con(self._ctx, self._ptr(P, 14), self._ptr(U, 14)), "rmhd_prim2con")
+        return U
+
+    def con2prim(self, U, P, status=None):
+        _check(lib().rmhd_con2prim(self._ctx, self._ptr(U, 14), self._ptr(P, 14),
+                                   self._ptr(status, None, torch.int32)), "rmhd_con2prim")
+        return P
+
+    def imex_stage(self, stage, dt, sigma, U_n, P_in, P_out, R_out=None, R1=None, R2=None, U_s=None, U_out=None,
+                   status=None):
+        b = StageBufs()
+        b.U_n = self._ptr(U_n, 14)
+        b.U_s = self._ptr(U_s, 14)
+        b.P_in = self._ptr(P_in, 14)
+        b.R1 = self._ptr(R1, 3)
+        b.R2 = self._ptr(R2, 3)
+        b.U_out = self._ptr(U_out, 14)
+        b.P_out = self._ptr(P_out, 14)
+        b.R_out = self._ptr(R_out, 3)
+        b.status = self._ptr(status, None, torch.int32)
+        _check(lib().rmhd_imex_stage(self._ctx, int(stage), float(dt), self._ptr(sigma), C.byref(b)),
+               "rmhd_imex_stage")
+
+    def step(self, dt, sigma, U, P):
+        _check(lib().rmhd_step(self._ctx, float(dt), self._ptr(sigma), self._ptr(U, 14), self._ptr(P, 14)),
+               "rmhd_step")
+
+    def max_signal_speed(self) -> float:
+        v = C.c_double()
+        _check(lib().rmhd_max_signal_speed(self._ctx, C.byref(v)), "rmhd_max_signal_speed")
+        return v.value
+
+    def failures(self) -> int:
+        v = C.c_int64()
+        _check(lib().rmhd_failures(self._ctx, C.byref(v)), "rmhd_failures")
+        return int(v.value)
+
+    def timing(self, enable=True):
+        _check(lib().rmhd_timing(self._ctx, 1 if enable else 0), "rmhd_timing")
+
+    def timing_read(self):
+        """{class: (milliseconds, launches)} since the last read (synchronises)."""
+        ms = (C.c_double * len(TIMING_CLASSES))()
+        n = (C.c_int64 * len(TIMING_CLASSES))()
+        _check(lib().rmhd_timing_read(self._ctx, ms, n), "rmhd_timing_read")
+        return {k: (ms[i], int(n[i])) for i, k in enumerate(TIMING_CLASSES)}
+
+    def close(self):
+        if self._ctx:
+            lib().rmhd_destroy(self._ctx)
+            self._ctx = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def grid_for(w, device="cuda", **kw) -> Grid:
+    """A Grid for a workload of ``paper_2510_18968_amd.workloads``."""
+    recon = {0: "minmod", 1: "mc2", 2: "weno5"}[w.recon]
+    d = make_desc(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=kw.pop("recon", recon), x0=w.x0, kappa=w.kappa,
+                  **kw)
+    return Grid(d, device)
