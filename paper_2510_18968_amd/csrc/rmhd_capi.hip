@@ -69,7 +69,6 @@ bool check_desc(const rmhd_grid_desc* d, std::string& why) {
     }
     if (d->recon < RMHD_RECON_MINMOD || d->recon > RMHD_RECON_WENO5) { why = "bad recon"; return false; }
     if (d->precision != RMHD_PREC_FP64 && d->precision != RMHD_PREC_MIXED) { why = "bad precision"; return false; }
-    if (d->precision == RMHD_PREC_MIXED) { why = "mixed precision is not available in this build"; return false; }
     if (!(d->gamma_ad > 1.0)) { why = "gamma_ad must be > 1"; return false; }
     if (!(d->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
     if (!(d->c2p_tol > 0.0) || d->c2p_maxit < 1) { why = "bad recovery tolerance or cap"; return false; }
@@ -140,41 +139,47 @@ int ghost_fill(rmhd_ctx* c, double* a, int nf) {
     return RMHD_OK;
 }
 
-template <int RECON, bool CURVED> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
+template <int RECON, bool CURVED, class R> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
     const Params& p = c->p;
     const long waves = (long)((p.n[0] + XSEG - 1) / XSEG) * p.n[1] * p.n[2];
     {
         Timed t(c, T_FX);
-        k_flux_x<RECON, CURVED><<<nblk(waves, 4), 256, 0, c->stream>>>(p, P, sig, c->rhs);
+        k_flux_x<RECON, CURVED, R><<<nblk(waves, 4), 256, 0, c->stream>>>(p, P, sig, c->rhs);
     }
     LAUNCH_CHECK();
     const int seglen = 32;
     if (is_active(p, 1)) {
         dim3 grid(nblk(p.n[0], 64), p.n[2], nblk(p.n[1], seglen));
         Timed t(c, T_FY);
-        k_flux_march<1, RECON, CURVED><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
+        k_flux_march<1, RECON, CURVED, R><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
         LAUNCH_CHECK();
     }
     if (is_active(p, 2)) {
         dim3 grid(nblk(p.n[0], 64), p.n[1], nblk(p.n[2], seglen));
         Timed t(c, T_FZ);
-        k_flux_march<2, RECON, CURVED><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
+        k_flux_march<2, RECON, CURVED, R><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
         LAUNCH_CHECK();
     }
     return RMHD_OK;
 }
 
-// minus the flux divergence of the (ghost-filled) primitives P into c->rhs
-int flux_div(rmhd_ctx* c, const double* P, const double* sig) {
+template <class R> int flux_div_r(rmhd_ctx* c, const double* P, const double* sig) {
     const int r = c->desc.recon;
     if (c->curved) {
-        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true>(c, P, sig);
-        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true>(c, P, sig);
-        return flux_div_t<REC_WENO5, true>(c, P, sig);
+        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R>(c, P, sig);
+        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R>(c, P, sig);
+        return flux_div_t<REC_WENO5, true, R>(c, P, sig);
     }
-    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false>(c, P, sig);
-    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false>(c, P, sig);
-    return flux_div_t<REC_WENO5, false>(c, P, sig);
+    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false, R>(c, P, sig);
+    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false, R>(c, P, sig);
+    return flux_div_t<REC_WENO5, false, R>(c, P, sig);
+}
+
+// minus the flux divergence of the (ghost-filled) primitives P into c->rhs;
+// FP32 reconstruction / HLLE / divergence in the mixed-precision form
+int flux_div(rmhd_ctx* c, const double* P, const double* sig) {
+    if (c->desc.precision == RMHD_PREC_MIXED) return flux_div_r<float>(c, P, sig);
+    return flux_div_r<double>(c, P, sig);
 }
 
 int stage1(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Pg, double* P1, double* R1,

@@ -56,9 +56,10 @@ template <class R> __device__ __forceinline__ void face_geo(const Params& p, lon
 }
 
 template <int D, class R> __device__ __forceinline__ void speeds(const Params& p, const Geo<R>& m, R& lp, R& lm) {
-    const R s = sqrt(m.gi[sidx(D, D)]);
+    const R gdd = m.gi[sidx(D, D)];
+    const R s = gdd * frsqrt(gdd);
     if (p.speed_mode == 0) {
-        const R b = m.bet[D] / m.alp;
+        const R b = m.bet[D] * frcp(m.alp);
         lp = s - b;
         lm = -s - b;
     } else {
@@ -82,24 +83,51 @@ template <int D, class R>
 __device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, const R* PL, const R* PR, R Jd, R* Fh) {
     R lp, lm;
     speeds<D>(p, m, lp, lm);
-    const R id = R(1) / (lp - lm);
+    const R id = frcp(lp - lm);
     const R cL = lp * id, cR = -lm * id, cU = lp * lm * id;
     const R G = R(p.G);
     R U[NF], F[NF];
-    prim2con(m, G, PL, U);
-    phys_flux<D>(m, G, PL, U, Jd, F);
+    state_flux<D>(m, G, PL, Jd, U, F);
 #pragma unroll
     for (int a = 0; a < NF; ++a) Fh[a] = cL * F[a] - cU * U[a];
-    prim2con(m, G, PR, U);
-    phys_flux<D>(m, G, PR, U, Jd, F);
+    __builtin_amdgcn_sched_barrier(0);
+    state_flux<D>(m, G, PR, Jd, U, F);
 #pragma unroll
     for (int a = 0; a < NF; ++a) Fh[a] += cR * F[a] + cU * U[a];
+}
+
+// Reconstruct the 14 fields of the cell at `o` along stride `s` to both faces.
+// Loads are software-pipelined one field ahead and a scheduling barrier per
+// field stops the compiler from hoisting all 70 stencil loads (which would
+// need ~140 extra VGPRs and cut occupancy to one wave per SIMD).  The cell
+// values of v, B, E and q are kept for the cell-centre current.
+template <int RECON, class R>
+__device__ __forceinline__ void recon_cell14(const double* __restrict__ P, long Np, long o, long s, R* fm, R* fp,
+                                             R* Pc) {
+    double cur[5], nxt[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) cur[q] = P[o + (q - 2) * s];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        if (f + 1 < NF) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) nxt[q] = P[(f + 1) * Np + o + (q - 2) * s];
+        }
+        const R st[5] = {R(cur[0]), R(cur[1]), R(cur[2]), R(cur[3]), R(cur[4])};
+        recon<RECON>(st, fm[f], fp[f]);
+        Pc[f] = st[2];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) cur[q] = nxt[q];
+    }
 }
 
 // ------------------------------------------------------------------ x fluxes
 constexpr int XSEG = 62;
 
-template <int RECON, bool CURVED>
+// R: arithmetic of reconstruction, HLLE and divergence (double, or float in
+// the mixed-precision form); state and rhs stay double.
+template <int RECON, bool CURVED, class R>
 __global__ __launch_bounds__(256) void k_flux_x(const Params p, const double* __restrict__ P,
                                                 const double* __restrict__ sig, double* __restrict__ rhs) {
     const int lane = threadIdx.x & 63;
@@ -117,53 +145,47 @@ __global__ __launch_bounds__(256) void k_flux_x(const Params p, const double* __
     const long o = ((long)k * p.np[1] + j) * p.np[0] + ic;
     const long Np = p.Np;
 
-    double fm[NF], fp[NF], Pc[NF];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        const double* a = P + f * Np + o;
-        const double s[5] = {a[-2], a[-1], a[0], a[1], a[2]};
-        recon<RECON>(s, fm[f], fp[f]);
-        Pc[f] = s[2];
-    }
+    R fm[NF], fp[NF], Pc[NF];
+    recon_cell14<RECON>(P, Np, o, 1, fm, fp, Pc);
     // cell-centre current, x component (charge flux at faces = mean of the two cells)
-    Geo<double> mc;
+    Geo<R> mc;
     if (CURVED) {
-        mc.alp = 1.0;
-        mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
-        for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
+        mc.alp = R(1);
+        mc.bet[0] = mc.bet[1] = mc.bet[2] = R(0);
+        for (int a = 0; a < 6; ++a) mc.g[a] = R(p.gam[a * Np + o]);
         geo_finish(mc);
     } else {
         geo_flat(mc);
     }
     const long os = o - ic + bc_map(p, 0, ic);
-    double J[3];
-    current(mc, Pc, sig[os], J);
-    const double JR = __shfl_down(J[0], 1);
-    double PR[NF];
+    R J[3];
+    current(mc, Pc, R(sig[os]), J);
+    const R JR = __shfl_down(J[0], 1);
+    R PR[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) PR[f] = __shfl_down(fm[f], 1);
 
     // face i + 1/2
-    Geo<double> m;
+    Geo<R> m;
     if (CURVED) face_geo(p, o, 1, m); else geo_flat(m);
     if (bad_state(m, fp))
-        for (int f = 0; f < NF; ++f) fp[f] = Pc[f];
+        for (int f = 0; f < NF; ++f) fp[f] = R(P[f * Np + o]);
     if (bad_state(m, PR))
-        for (int f = 0; f < NF; ++f) PR[f] = P[f * Np + o + 1];
-    double Fh[NF];
-    face_flux<0>(p, m, fp, PR, 0.5 * (J[0] + JR), Fh);
+        for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + o + 1]);
+    R Fh[NF];
+    face_flux<0>(p, m, fp, PR, R(0.5) * (J[0] + JR), Fh);
 
     const bool cell = lane >= 1 && lane <= XSEG && i >= p.g[0] && i < ilast;
-    const double ih = p.idx[0];
+    const R ih = R(p.idx[0]);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        const double Fl = __shfl_up(Fh[f], 1);
-        if (cell) rhs[f * Np + o] = -(Fh[f] - Fl) * ih;
+        const R Fl = __shfl_up(Fh[f], 1);
+        if (cell) rhs[f * Np + o] = double(-(Fh[f] - Fl) * ih);
     }
 }
 
 // -------------------------------------------------------------- y / z fluxes
-template <int D, int RECON, bool CURVED>
+template <int D, int RECON, bool CURVED, class R>
 __global__ __launch_bounds__(64) void k_flux_march(const Params p, const double* __restrict__ P,
                                                    const double* __restrict__ sig, double* __restrict__ rhs,
                                                    int seglen) {
@@ -176,46 +198,41 @@ __global__ __launch_bounds__(64) void k_flux_march(const Params p, const double*
     const long s = p.st[D];
     const long Np = p.Np;
     const long base = (long)(i + p.g[0]) + (long)e * p.st[E];
-    const double ih = p.idx[D];
+    const R ih = R(p.idx[D]);
 
-    double PLc[NF], Fprev[NF], Jprev = 0.0;
+    R PLc[NF], Fprev[NF], Jprev = R(0);
+#pragma unroll 1
     for (int c = c0 - 1; c <= c1; ++c) {
         const int cp = c + p.g[D];
         const long o = base + (long)cp * s;
-        double fm[NF], fp[NF], Pc[NF];
-#pragma unroll
-        for (int f = 0; f < NF; ++f) {
-            const double* a = P + f * Np + o;
-            const double st5[5] = {a[-2 * s], a[-s], a[0], a[s], a[2 * s]};
-            recon<RECON>(st5, fm[f], fp[f]);
-            Pc[f] = st5[2];
-        }
-        Geo<double> mc;
+        R fm[NF], fp[NF], Pc[NF];
+        recon_cell14<RECON>(P, Np, o, s, fm, fp, Pc);
+        Geo<R> mc;
         if (CURVED) {
-            mc.alp = 1.0;
-            mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
-            for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
+            mc.alp = R(1);
+            mc.bet[0] = mc.bet[1] = mc.bet[2] = R(0);
+            for (int a = 0; a < 6; ++a) mc.g[a] = R(p.gam[a * Np + o]);
             geo_finish(mc);
         } else {
             geo_flat(mc);
         }
         const long os = o + (long)(bc_map(p, D, cp) - cp) * s;
-        double J[3];
-        current(mc, Pc, sig[os], J);
+        R J[3];
+        current(mc, Pc, R(sig[os]), J);
         if (c >= c0) {
             // face between c - 1 and c
-            Geo<double> m;
+            Geo<R> m;
             if (CURVED) face_geo(p, o - s, s, m); else geo_flat(m);
             if (bad_state(m, PLc))
-                for (int f = 0; f < NF; ++f) PLc[f] = P[f * Np + o - s];
+                for (int f = 0; f < NF; ++f) PLc[f] = R(P[f * Np + o - s]);
             if (bad_state(m, fm))
-                for (int f = 0; f < NF; ++f) fm[f] = Pc[f];
-            double Fh[NF];
-            face_flux<D>(p, m, PLc, fm, 0.5 * (Jprev + J[D]), Fh);
+                for (int f = 0; f < NF; ++f) fm[f] = R(P[f * Np + o]);
+            R Fh[NF];
+            face_flux<D>(p, m, PLc, fm, R(0.5) * (Jprev + J[D]), Fh);
             if (c > c0) {
                 const long oc = o - s;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) rhs[f * Np + oc] -= (Fh[f] - Fprev[f]) * ih;
+                for (int f = 0; f < NF; ++f) rhs[f * Np + oc] -= double((Fh[f] - Fprev[f]) * ih);
             }
 #pragma unroll
             for (int f = 0; f < NF; ++f) Fprev[f] = Fh[f];
@@ -303,6 +320,24 @@ __device__ __forceinline__ void write_prims(const Params& p, long o, const Geo<d
         P[(I_E + i) * p.Np + o] = Ec[i] * m.isg;
     }
     for (int f = I_PHI; f < NF; ++f) P[f * p.Np + o] = U[f] * m.isg;
+}
+
+// primitives at a recovered root from RecIn (D, Bcal) and the cleaning and
+// charge rows of the conserved array U (global)
+__device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo<double>& m, const RecIn& k,
+                                              const double* U, const double* x, const double* Ec, double* P) {
+    const double* v = x + 1;
+    double vl[3];
+    lower(m.g, v, vl);
+    const double W = frsqrt(1.0 - dot3(vl, v));
+    P[I_RHO * p.Np + o] = k.D * m.isg / W;
+    P[I_P * p.Np + o] = x[0];
+    for (int i = 0; i < 3; ++i) {
+        P[(I_V + i) * p.Np + o] = v[i];
+        P[(I_B + i) * p.Np + o] = k.Bc[i] * m.isg;
+        P[(I_E + i) * p.Np + o] = Ec[i] * m.isg;
+    }
+    for (int f = I_PHI; f < NF; ++f) P[f * p.Np + o] = U[f * p.Np + o] * m.isg;
 }
 
 __device__ __forceinline__ void copy_prims(const Params& p, long o, const double* Pg, double* P) {
@@ -433,37 +468,44 @@ __global__ __launch_bounds__(256) void k_stage1(const Params p, double dt, const
                                                 unsigned long long* nfail) {
     long o;
     if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    const long Np = p.Np;
     Geo<double> m;
     cell_geo<CURVED>(p, o, m);
-    double Uc[NF];
-    for (int f = 0; f < NF; ++f) Uc[f] = Un[f * p.Np + o];
     RecIn k;
-    rec_setup(p, m, Uc, k);
+    {
+        double Uc[NF];
+        for (int f = 0; f < NF; ++f) Uc[f] = Un[f * Np + o];
+        rec_setup(p, m, Uc, k);
+        for (int i = 0; i < 3; ++i) k.Es[i] = Uc[I_E + i];
+        if (U1)
+            for (int f = 0; f < NF; ++f)
+                if (f < I_E || f >= I_E + 3) U1[f * Np + o] = Uc[f];
+    }
     const double gdt = GAM_IMEX() * dt;
-    for (int i = 0; i < 3; ++i) k.Es[i] = Uc[I_E + i];
     k.cfac = gdt * m.alp * sig[o];
-    double x[4] = {Pg_[I_P * p.Np + o], Pg_[I_V * p.Np + o], Pg_[(I_V + 1) * p.Np + o], Pg_[(I_V + 2) * p.Np + o]};
+    double x[4] = {Pg_[I_P * Np + o], Pg_[I_V * Np + o], Pg_[(I_V + 1) * Np + o], Pg_[(I_V + 2) * Np + o]};
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
+    __builtin_amdgcn_sched_barrier(0);
     if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
     else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
+    __builtin_amdgcn_sched_barrier(0);
     if (st >= 0) {
-        write_prims(p, o, m, Uc, x, E, P1);
+        write_prims_k(p, o, m, k, Un, x, E, P1);
     } else {
-        for (int f = 0; f < NF; ++f) P1[f * p.Np + o] = Pg_[f * p.Np + o];
+        for (int f = 0; f < NF; ++f) P1[f * Np + o] = Pg_[f * Np + o];
         for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
         atomicAdd(nfail, 1ull);
     }
-    for (int i = 0; i < 3; ++i) R1[i * p.Np + o] = (E[i] - k.Es[i]) / gdt;
-    if (U1) {
-        for (int f = 0; f < NF; ++f) U1[f * p.Np + o] = Uc[f];
-        for (int i = 0; i < 3; ++i) U1[(I_E + i) * p.Np + o] = E[i];
-    }
+    for (int i = 0; i < 3; ++i) R1[i * Np + o] = (E[i] - k.Es[i]) / gdt;
+    if (U1)
+        for (int i = 0; i < 3; ++i) U1[(I_E + i) * Np + o] = E[i];
     if (status) status[o] = st;
 }
 
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
-// divergence of P_s has been accumulated into rhs
+// divergence of P_s has been accumulated into rhs.  Output rows are written
+// as soon as they are known so that little stays live across the recovery.
 template <int STAGE, bool CURVED>
 __global__ __launch_bounds__(256) void k_update(const Params p, double dt, const double* __restrict__ sig,
                                                 const double* __restrict__ Un, const double* __restrict__ Us,
@@ -477,59 +519,64 @@ __global__ __launch_bounds__(256) void k_update(const Params p, double dt, const
     const long Np = p.Np;
     Geo<double> m;
     cell_geo<CURVED>(p, o, m);
-    double Pc[NF], L[NF];
-    {
-        double Uc[NF], S[NF];
-        for (int f = 0; f < NF; ++f) Pc[f] = Ps[f * Np + o];
-        prim2con(m, p.G, Pc, Uc);
-        sources<CURVED>(p, o, m, Pc, Uc, S);
-        for (int f = 0; f < NF; ++f) L[f] = rhs[f * Np + o] + S[f];
-    }
     const double g = GAM_IMEX();
-    double Y[NF];
-    if (STAGE == 2) {
-        for (int f = 0; f < NF; ++f) Y[f] = Un[f * Np + o] + dt * L[f];
-        double Es[3];
-        for (int i = 0; i < 3; ++i) Es[i] = Y[I_E + i] + dt * (1.0 - 2.0 * g) * R1[i * Np + o];
-        RecIn k;
+    RecIn k;
+    double x[4];
+    {
+        double Y[NF];
+        {
+            double Pc[NF], Uc[NF], S[NF];
+            for (int f = 0; f < NF; ++f) Pc[f] = Ps[f * Np + o];
+            prim2con(m, p.G, Pc, Uc);
+            sources<CURVED>(p, o, m, Pc, Uc, S);
+            x[0] = Pc[I_P];
+            x[1] = Pc[I_V];
+            x[2] = Pc[I_V + 1];
+            x[3] = Pc[I_V + 2];
+            if (STAGE == 2) {
+                for (int f = 0; f < NF; ++f) Y[f] = Un[f * Np + o] + dt * (rhs[f * Np + o] + S[f]);
+            } else {
+                // U^{n+1} = (U^n + U(2))/2 + dt/2 F(U(2)) + dt/2 (2 gamma R1 + (1 - gamma) R2) on E
+                for (int f = 0; f < NF; ++f)
+                    Y[f] = 0.5 * (Un[f * Np + o] + Us[f * Np + o]) + 0.5 * dt * (rhs[f * Np + o] + S[f]);
+                for (int i = 0; i < 3; ++i)
+                    Y[I_E + i] += 0.5 * dt * (2.0 * g * R1[i * Np + o] + (1.0 - g) * R2[i * Np + o]);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        for (int f = 0; f < NF; ++f)
+            if (STAGE == 3 || f < I_E || f >= I_E + 3) Uo[f * Np + o] = Y[f];
         rec_setup(p, m, Y, k);
-        for (int i = 0; i < 3; ++i) k.Es[i] = Es[i];
+        if (STAGE == 2)
+            for (int i = 0; i < 3; ++i) k.Es[i] = Y[I_E + i] + dt * (1.0 - 2.0 * g) * R1[i * Np + o];
+        else
+            for (int i = 0; i < 3; ++i) k.Es[i] = Y[I_E + i];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
+    int it, st;
+    if (STAGE == 2) {
         k.cfac = g * dt * m.alp * sig[o];
-        double x[4] = {Pc[I_P], Pc[I_V], Pc[I_V + 1], Pc[I_V + 2]};
-        double E[3] = {Es[0], Es[1], Es[2]};
-        int it, st;
         if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
         else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
-        if (st >= 0) {
-            write_prims(p, o, m, Y, x, E, Po);
-        } else {
-            copy_prims(p, o, Pc, Po);
-            for (int i = 0; i < 3; ++i) E[i] = Es[i];
-            atomicAdd(nfail, 1ull);
-        }
-        for (int f = 0; f < NF; ++f) Uo[f * Np + o] = (f >= I_E && f < I_E + 3) ? E[f - I_E] : Y[f];
-        for (int i = 0; i < 3; ++i) Ro[i * Np + o] = (E[i] - Es[i]) / (g * dt);
-        if (status) status[o] = st;
     } else {
-        // U^{n+1} = (U^n + U(2))/2 + dt/2 F(U(2)) + dt/2 (2 gamma R1 + (1 - gamma) R2) on E
-        for (int f = 0; f < NF; ++f) Y[f] = 0.5 * (Un[f * Np + o] + Us[f * Np + o]) + 0.5 * dt * L[f];
-        for (int i = 0; i < 3; ++i)
-            Y[I_E + i] += 0.5 * dt * (2.0 * g * R1[i * Np + o] + (1.0 - g) * R2[i * Np + o]);
-        RecIn k;
-        rec_setup(p, m, Y, k);
-        double x[4] = {Pc[I_P], Pc[I_V], Pc[I_V + 1], Pc[I_V + 2]};
-        const double E[3] = {Y[I_E], Y[I_E + 1], Y[I_E + 2]};
-        int it;
-        const int st = recover_plain(k, E, x, p.tol, p.maxit, &it);
-        for (int f = 0; f < NF; ++f) Uo[f * Np + o] = Y[f];
-        if (st >= 0) {
-            write_prims(p, o, m, Y, x, E, Po);
-        } else {
-            copy_prims(p, o, Pc, Po);
-            atomicAdd(nfail, 1ull);
-        }
-        if (status) status[o] = st;
+        st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    if (st >= 0) {
+        write_prims_k(p, o, m, k, Uo, x, E, Po);
+    } else {
+        for (int f = 0; f < NF; ++f) Po[f * Np + o] = Ps[f * Np + o];
+        for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
+        atomicAdd(nfail, 1ull);
+    }
+    if (STAGE == 2) {
+        for (int i = 0; i < 3; ++i) {
+            Uo[(I_E + i) * Np + o] = E[i];
+            Ro[i * Np + o] = (E[i] - k.Es[i]) / (g * dt);
+        }
+    }
+    if (status) status[o] = st;
 }
 
 // ---------------------------------------------------- max signal speed (CFL)

@@ -15,6 +15,25 @@ namespace rmhd {
 
 using ::sqrt;
 
+// FP64 reciprocal / reciprocal square root: hardware estimate refined by two
+// Newton steps (about 1 ulp; no IEEE scaling or fix-up, so arguments must be
+// finite and nonzero -- every call site divides by a positive quantity).
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ double frsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = y * fma(-h * y, y, 1.5);
+    return y * fma(-h * y, y, 1.5);
+}
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float frsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+
 constexpr int NF = 14;
 enum : int { I_RHO = 0, I_P = 1, I_V = 2, I_B = 5, I_E = 8, I_PHI = 11, I_PSI = 12, I_Q = 13 };
 enum : int { I_D = 0, I_S = 1, I_TAU = 4 };
@@ -46,15 +65,16 @@ template <class R> __device__ __forceinline__ void geo_finish(Geo<R>& m) {
     const R cxy = gxz * gyz - gxy * gzz;
     const R cxz = gxy * gyz - gxz * gyy;
     const R det = gxx * cxx + gxy * cxy + gxz * cxz;
-    const R id = R(1) / det;
+    const R rs = frsqrt(det);
+    const R id = rs * rs;
     m.gi[0] = cxx * id;
     m.gi[1] = cxy * id;
     m.gi[2] = cxz * id;
     m.gi[3] = (gxx * gzz - gxz * gxz) * id;
     m.gi[4] = (gxy * gxz - gxx * gyz) * id;
     m.gi[5] = (gxx * gyy - gxy * gxy) * id;
-    m.sg = sqrt(det);
-    m.isg = R(1) / m.sg;
+    m.sg = det * rs;
+    m.isg = rs;
 }
 
 template <class R> __device__ __forceinline__ void lower(const R* g, const R* u, R* l) {
@@ -81,8 +101,8 @@ template <class R> __device__ __forceinline__ void prim2con(const Geo<R>& m, R G
     lower(m.g, v, vl);
     lower(m.g, B, Bl);
     lower(m.g, E, El);
-    const R W2 = R(1) / (R(1) - dot3(vl, v));
-    const R W = sqrt(W2);
+    const R W = frsqrt(R(1) - dot3(vl, v));
+    const R W2 = W * W;
     const R hW2 = (P[I_RHO] + G / (G - R(1)) * P[I_P]) * W2;
     const R em = R(0.5) * (dot3(El, E) + dot3(Bl, B));
     cross(E, B, c);   // eta_ijk E^j B^k; epsilon_ijk = sqrt(gamma) eta_ijk
@@ -101,34 +121,43 @@ template <class R> __device__ __forceinline__ void current(const Geo<R>& m, cons
     lower(m.g, v, vl);
     lower(m.g, P + I_B, Bl);
     cross(vl, Bl, vb);
-    const R W = R(1) / sqrt(R(1) - dot3(vl, v));
+    const R W = frsqrt(R(1) - dot3(vl, v));
     const R Ec[3] = {m.sg * P[I_E], m.sg * P[I_E + 1], m.sg * P[I_E + 2]};
     const R vE = dot3(vl, Ec);
     const R Q = m.sg * P[I_Q];
     for (int i = 0; i < 3; ++i) J[i] = Q * v[i] + W * sigma * (Ec[i] + vb[i] - vE * v[i]);
 }
 
-// physical flux along D (eq. GRRMHD_flux_form, sqrt(gamma) once); Jd is the
+// conserved variables and physical flux along D of one state (eqs.
+// conserved_*, GRRMHD_flux_form with sqrt(gamma) counted once); Jd is the
 // current carried by the charge flux at this face
 template <int D, class R>
-__device__ __forceinline__ void phys_flux(const Geo<R>& m, R G, const R* P, const R* U, R Jd, R* F) {
+__device__ __forceinline__ void state_flux(const Geo<R>& m, R G, const R* P, R Jd, R* U, R* F) {
     const R* v = P + I_V;
     const R* B = P + I_B;
     const R* E = P + I_E;
-    R vl[3], Bl[3], El[3];
+    R vl[3], Bl[3], El[3], c[3];
     lower(m.g, v, vl);
     lower(m.g, B, Bl);
     lower(m.g, E, El);
-    const R W2 = R(1) / (R(1) - dot3(vl, v));
-    const R hW2 = (P[I_RHO] + G / (G - R(1)) * P[I_P]) * W2;
-    const R pt = P[I_P] + R(0.5) * (dot3(El, E) + dot3(Bl, B));
-    const R a = m.alp, bd = m.bet[D], as = m.alp * m.sg;
+    const R W = frsqrt(R(1) - dot3(vl, v));
+    const R hW2 = (P[I_RHO] + G / (G - R(1)) * P[I_P]) * (W * W);
+    const R em = R(0.5) * (dot3(El, E) + dot3(Bl, B));
+    const R pt = P[I_P] + em;
+    cross(E, B, c);
+    const R sg = m.sg;
+    const R Dd = sg * P[I_RHO] * W;
+    U[I_D] = Dd;
+    for (int i = 0; i < 3; ++i) U[I_S + i] = sg * (hW2 * vl[i] + sg * c[i]);
+    U[I_TAU] = sg * (hW2 - P[I_P] + em) - Dd;
+    for (int a = I_B; a < NF; ++a) U[a] = sg * P[a];
+    const R a = m.alp, bd = m.bet[D], as = m.alp * sg;
     const R vd = v[D], Ed = E[D], Bd = B[D];
-    F[I_D] = (a * vd - bd) * U[I_D];
+    F[I_D] = (a * vd - bd) * Dd;
     for (int i = 0; i < 3; ++i)
         F[I_S + i] = as * (hW2 * vd * vl[i] - Ed * El[i] - Bd * Bl[i] + (i == D ? pt : R(0))) - bd * U[I_S + i];
     const R Sd = m.gi[sidx(D, 0)] * U[I_S] + m.gi[sidx(D, 1)] * U[I_S + 1] + m.gi[sidx(D, 2)] * U[I_S + 2];
-    F[I_TAU] = a * (Sd - vd * U[I_D]) - bd * U[I_TAU];
+    F[I_TAU] = a * (Sd - vd * Dd) - bd * U[I_TAU];
     // (e_D x X)^i for covariant X
     R eE[3], eB[3];
     if (D == 0) { eE[0] = R(0); eE[1] = -El[2]; eE[2] = El[1]; eB[0] = R(0); eB[1] = -Bl[2]; eB[2] = Bl[1]; }
@@ -153,33 +182,30 @@ template <class R> __device__ __forceinline__ R mm2(R a, R b) {
 // face values of the middle cell of s[0..4]: fm at i-1/2, fp at i+1/2
 template <int RECON, class R> __device__ __forceinline__ void recon(const R* s, R& fm, R& fp) {
     if constexpr (RECON == REC_WENO5) {
+        // WENO5-JS weights a_k = d_k / (eps + beta_k)^2 over the common
+        // denominator e0 e1 e2: two divisions per cell instead of five; the
+        // smoothness indicators are shared by the two faces
         const R eps = R(1e-6);
         const R t0 = s[0] - R(2) * s[1] + s[2], u0 = s[0] - R(4) * s[1] + R(3) * s[2];
         const R t1 = s[1] - R(2) * s[2] + s[3], u1 = s[1] - s[3];
         const R t2 = s[2] - R(2) * s[3] + s[4], u2 = R(3) * s[2] - R(4) * s[3] + s[4];
         const R c13 = R(13) / R(12);
-        const R b0 = c13 * t0 * t0 + R(0.25) * u0 * u0;
-        const R b1 = c13 * t1 * t1 + R(0.25) * u1 * u1;
-        const R b2 = c13 * t2 * t2 + R(0.25) * u2 * u2;
-        const R e0 = eps + b0, e1 = eps + b1, e2 = eps + b2;
-        const R w0 = R(1) / (e0 * e0), w1 = R(1) / (e1 * e1), w2 = R(1) / (e2 * e2);
-        const R i6 = R(1) / R(6);
-        // right face: stencils {i-2..i}, {i-1..i+1}, {i..i+2}, ideal weights 1/10, 6/10, 3/10
-        {
-            const R q0 = (R(2) * s[0] - R(7) * s[1] + R(11) * s[2]) * i6;
-            const R q1 = (-s[1] + R(5) * s[2] + R(2) * s[3]) * i6;
-            const R q2 = (R(2) * s[2] + R(5) * s[3] - s[4]) * i6;
-            const R a0 = R(0.1) * w0, a1 = R(0.6) * w1, a2 = R(0.3) * w2;
-            fp = (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
-        }
-        // left face: mirror image, same smoothness indicators
-        {
-            const R q0 = (R(2) * s[4] - R(7) * s[3] + R(11) * s[2]) * i6;
-            const R q1 = (-s[3] + R(5) * s[2] + R(2) * s[1]) * i6;
-            const R q2 = (R(2) * s[2] + R(5) * s[1] - s[0]) * i6;
-            const R a0 = R(0.1) * w2, a1 = R(0.6) * w1, a2 = R(0.3) * w0;
-            fm = (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
-        }
+        const R e0 = eps + (c13 * t0 * t0 + R(0.25) * u0 * u0);
+        const R e1 = eps + (c13 * t1 * t1 + R(0.25) * u1 * u1);
+        const R e2 = eps + (c13 * t2 * t2 + R(0.25) * u2 * u2);
+        const R s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+        const R p12 = s1 * s2, p02 = s0 * s2, p01 = s0 * s1;
+        // six times the candidate values
+        const R q0 = R(2) * s[0] - R(7) * s[1] + R(11) * s[2];
+        const R q1 = -s[1] + R(5) * s[2] + R(2) * s[3];
+        const R q2 = R(2) * s[2] + R(5) * s[3] - s[4];
+        const R r0 = R(2) * s[4] - R(7) * s[3] + R(11) * s[2];
+        const R r1 = -s[3] + R(5) * s[2] + R(2) * s[1];
+        const R r2 = R(2) * s[2] + R(5) * s[1] - s[0];
+        const R ap0 = R(0.1) * p12, ap1 = R(0.6) * p02, ap2 = R(0.3) * p01;   // right face
+        const R am0 = R(0.1) * p01, am1 = R(0.6) * p02, am2 = R(0.3) * p12;   // left face (mirror)
+        fp = (ap0 * q0 + ap1 * q1 + ap2 * q2) * frcp(R(6) * (ap0 + ap1 + ap2));
+        fm = (am0 * r0 + am1 * r1 + am2 * r2) * frcp(R(6) * (am0 + am1 + am2));
     } else {
         const R dm = s[2] - s[1], dp = s[3] - s[2];
         R sl;
@@ -222,24 +248,54 @@ __device__ __forceinline__ D4 operator-(double b, const D4& a) {
     return D4{b - a.v, {-a.d[0], -a.d[1], -a.d[2], -a.d[3]}};
 }
 __device__ __forceinline__ D4 recip(const D4& a) {
-    const double r = 1.0 / a.v, r2 = -r * r;
+    const double r = frcp(a.v), r2 = -r * r;
     return D4{r, {a.d[0] * r2, a.d[1] * r2, a.d[2] * r2, a.d[3] * r2}};
 }
 __device__ __forceinline__ D4 operator/(const D4& a, const D4& b) { return a * recip(b); }
 __device__ __forceinline__ D4 operator/(const D4& a, double b) { return a * (1.0 / b); }
 __device__ __forceinline__ D4 operator/(double a, const D4& b) { return a * recip(b); }
-__device__ __forceinline__ D4 sqrt(const D4& a) {
-    const double s = ::sqrt(a.v), h = 0.5 / s;
-    return D4{s, {a.d[0] * h, a.d[1] * h, a.d[2] * h, a.d[3] * h}};
+__device__ __forceinline__ D4 rsq(const D4& a) {
+    const double r = frsqrt(a.v), h = -0.5 * r * r * r;
+    return D4{r, {a.d[0] * h, a.d[1] * h, a.d[2] * h, a.d[3] * h}};
 }
+__device__ __forceinline__ D4 inv(const D4& a) { return recip(a); }
+__device__ __forceinline__ double rsq(double a) { return frsqrt(a); }
+__device__ __forceinline__ double inv(double a) { return frcp(a); }
 __device__ __forceinline__ double val(double x) { return x; }
 __device__ __forceinline__ double val(const D4& x) { return x.v; }
+
+// one-direction dual number (value, derivative): Jacobian columns one at a
+// time keep 2 doubles per intermediate instead of 5
+struct D1 {
+    double v, d;
+};
+__device__ __forceinline__ D1 operator+(const D1& a, const D1& b) { return D1{a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ D1 operator-(const D1& a, const D1& b) { return D1{a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ D1 operator*(const D1& a, const D1& b) { return D1{a.v * b.v, fma(a.d, b.v, a.v * b.d)}; }
+__device__ __forceinline__ D1 operator*(double a, const D1& b) { return D1{a * b.v, a * b.d}; }
+__device__ __forceinline__ D1 operator*(const D1& b, double a) { return D1{a * b.v, a * b.d}; }
+__device__ __forceinline__ D1 operator+(const D1& a, double b) { return D1{a.v + b, a.d}; }
+__device__ __forceinline__ D1 operator+(double b, const D1& a) { return D1{a.v + b, a.d}; }
+__device__ __forceinline__ D1 operator-(const D1& a, double b) { return D1{a.v - b, a.d}; }
+__device__ __forceinline__ D1 operator-(double b, const D1& a) { return D1{b - a.v, -a.d}; }
+__device__ __forceinline__ D1 operator-(const D1& a) { return D1{-a.v, -a.d}; }
+__device__ __forceinline__ D1 inv(const D1& a) {
+    const double r = frcp(a.v);
+    return D1{r, -a.d * r * r};
+}
+__device__ __forceinline__ D1 rsq(const D1& a) {
+    const double r = frsqrt(a.v);
+    return D1{r, -0.5 * a.d * r * r * r};
+}
+__device__ __forceinline__ D1 operator/(const D1& a, const D1& b) { return a * inv(b); }
+__device__ __forceinline__ D1 operator/(double a, const D1& b) { return a * inv(b); }
+__device__ __forceinline__ D1 operator/(const D1& a, double b) { return a * (1.0 / b); }
+__device__ __forceinline__ double val(const D1& x) { return x.v; }
 
 // constant inputs of one recovery
 struct RecIn {
     double G, D, tau, S[3], Bc[3], Bl[3], Es[3], cfac;   // cfac = a dt alpha sigma
     double sg, isg, g[6], gi[6];
-    double ExBs[3];   // not used by the stiff residual
 };
 
 // Residual of the recovery map at x = (p, v): r0 = (Gamma-1) rho eps - p,
@@ -254,15 +310,15 @@ __device__ __forceinline__ bool rec_residual(const RecIn& k, const S* x, S* r, d
     for (int i = 0; i < 3; ++i) vl[i] = k.g[sidx(i, 0)] * v[0] + k.g[sidx(i, 1)] * v[1] + k.g[sidx(i, 2)] * v[2];
     const S v2 = vl[0] * v[0] + vl[1] * v[1] + vl[2] * v[2];
     if (!(val(v2) < 1.0) || !(val(p) > 0.0)) return false;
-    const S W = 1.0 / sqrt(1.0 - v2);
+    const S W = rsq(1.0 - v2);
     const S c = k.cfac * W;
     // b = E* - c (v_l x B_l); (1 + c) E - c (v_l . E) v = b
     S b[3];
     b[0] = k.Es[0] - c * (vl[1] * k.Bl[2] - vl[2] * k.Bl[1]);
     b[1] = k.Es[1] - c * (vl[2] * k.Bl[0] - vl[0] * k.Bl[2]);
     b[2] = k.Es[2] - c * (vl[0] * k.Bl[1] - vl[1] * k.Bl[0]);
-    const S vE = (vl[0] * b[0] + vl[1] * b[1] + vl[2] * b[2]) / (1.0 + c * (1.0 - v2));
-    const S i1c = 1.0 / (1.0 + c);
+    const S vE = (vl[0] * b[0] + vl[1] * b[1] + vl[2] * b[2]) * inv(1.0 + c * (1.0 - v2));
+    const S i1c = inv(1.0 + c);
     S E[3];
     for (int i = 0; i < 3; ++i) E[i] = (b[i] + c * vE * v[i]) * i1c;
     S El[3];
@@ -270,7 +326,7 @@ __device__ __forceinline__ bool rec_residual(const RecIn& k, const S* x, S* r, d
     const S em = (El[0] * E[0] + El[1] * E[1] + El[2] * E[2] +
                   (k.Bl[0] * k.Bc[0] + k.Bl[1] * k.Bc[1] + k.Bl[2] * k.Bc[2]) * k.sg) * (0.5 * k.isg);
     const S den = k.tau + k.D + k.sg * p - em;
-    const S iden = 1.0 / den;
+    const S iden = inv(den);
     S wl[3];
     wl[0] = (k.S[0] - (E[1] * k.Bc[2] - E[2] * k.Bc[1])) * iden;
     wl[1] = (k.S[1] - (E[2] * k.Bc[0] - E[0] * k.Bc[2])) * iden;
@@ -279,11 +335,11 @@ __device__ __forceinline__ bool rec_residual(const RecIn& k, const S* x, S* r, d
     for (int i = 0; i < 3; ++i) w[i] = k.gi[sidx(i, 0)] * wl[0] + k.gi[sidx(i, 1)] * wl[1] + k.gi[sidx(i, 2)] * wl[2];
     const S w2 = wl[0] * w[0] + wl[1] * w[1] + wl[2] * w[2];
     if (!(val(w2) < 1.0)) return false;
-    const S Wn2 = 1.0 / (1.0 - w2);
-    const S Wn = sqrt(Wn2);
-    const S DW = k.D * Wn;
-    const S rho = k.D * k.isg / Wn;
-    const S eps = (k.tau - k.D * (Wn - 1.0) - k.sg * p * (Wn2 - 1.0) - em) / DW;
+    const S Wn = rsq(1.0 - w2);
+    const S Wn2 = Wn * Wn;
+    const S iW = inv(Wn);
+    const S rho = k.D * k.isg * iW;
+    const S eps = (k.tau - k.D * (Wn - 1.0) - k.sg * p * (Wn2 - 1.0) - em) * (iW * inv(k.D));
     r[0] = (k.G - 1.0) * rho * eps - p;
     for (int i = 0; i < 3; ++i) r[1 + i] = w[i] - v[i];
     if (Eout)
@@ -296,46 +352,79 @@ __device__ __forceinline__ double rec_merit(const double* r, double p) {
     return a * a + r[1] * r[1] + r[2] * r[2] + r[3] * r[3];
 }
 
-// 4x4 Gaussian elimination with partial pivoting, in place; false if singular
-__device__ __forceinline__ bool solve4(double A[4][4], double* b) {
+// LU factorisation of a 4x4 matrix with partial pivoting, in place
+__device__ __forceinline__ bool lu4(double A[4][4], int* piv) {
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        int piv = c;
+        int pv = c;
         double best = fabs(A[c][c]);
 #pragma unroll
         for (int r = c + 1; r < 4; ++r)
-            if (fabs(A[r][c]) > best) { best = fabs(A[r][c]); piv = r; }
+            if (fabs(A[r][c]) > best) { best = fabs(A[r][c]); pv = r; }
+        piv[c] = pv;
         if (best == 0.0) return false;
-        if (piv != c) {
+        if (pv != c) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) { double t = A[c][k]; A[c][k] = A[piv][k]; A[piv][k] = t; }
-            double t = b[c]; b[c] = b[piv]; b[piv] = t;
+            for (int k = 0; k < 4; ++k) { const double t = A[c][k]; A[c][k] = A[pv][k]; A[pv][k] = t; }
         }
         const double ic = 1.0 / A[c][c];
+        A[c][c] = ic;                              // keep the reciprocal pivot
 #pragma unroll
         for (int r = c + 1; r < 4; ++r) {
             const double f = A[r][c] * ic;
+            A[r][c] = f;
 #pragma unroll
-            for (int k = c; k < 4; ++k) A[r][k] -= f * A[c][k];
-            b[r] -= f * b[c];
+            for (int k = c + 1; k < 4; ++k) A[r][k] -= f * A[c][k];
         }
+    }
+    return true;
+}
+// solve with the factors of lu4: the factorisation swaps whole rows, so the
+// complete permutation is applied to b before the forward substitution
+__device__ __forceinline__ void lu4_solve(const double A[4][4], const int* piv, double* b) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+        if (piv[c] != c) { const double t = b[c]; b[c] = b[piv[c]]; b[piv[c]] = t; }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+        for (int r = c + 1; r < 4; ++r) b[r] -= A[r][c] * b[c];
     }
 #pragma unroll
     for (int r = 3; r >= 0; --r) {
-        double s = b[r];
+        double t = b[r];
 #pragma unroll
-        for (int k = r + 1; k < 4; ++k) s -= A[r][k] * b[k];
-        b[r] = s / A[r][r];
+        for (int k = r + 1; k < 4; ++k) t -= A[r][k] * b[k];
+        b[r] = t * A[r][r];
     }
-    return true;
 }
 
 enum : int { ST_OK = 0, ST_WARN = 1, ST_NOCONV = -3, ST_UNPHYS = -4 };
 
-// Stiff coupled solve: Newton with the exact Jacobian (dual numbers) on the
-// recovery map; converges to the root the paper's iteration converges to
-// and stays convergent where that iteration does not (B^2 > h W^2).
-// x in/out: guess -> root (p, v^i); E out: densitised E at the root.
+// exact Jacobian of the recovery map at x, one dual direction per column,
+// factorised in place; r = residual at x
+__device__ __forceinline__ bool rec_jacobian(const RecIn& k, const double* x, double J[4][4], int* piv, double* r) {
+#pragma unroll 1
+    for (int b = 0; b < 4; ++b) {
+        D1 xd[4], rd[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) xd[a] = D1{x[a], a == b ? 1.0 : 0.0};
+        if (!rec_residual<D1>(k, xd, rd, nullptr)) return false;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            r[a] = rd[a].v;
+            J[a][b] = rd[a].d;
+        }
+    }
+    return lu4(J, piv);
+}
+
+// Stiff coupled solve: the root of the recovery map r(p, v) (the fixed point
+// the paper's iteration converges to where it converges), by Newton's method
+// with the exact Jacobian, kept between iterations while the steps contract
+// fast (chord steps) and refreshed otherwise; backtracking keeps the state
+// physical and the residual decreasing.  x in/out: guess -> (p, v^i);
+// E out: densitised E at the root.
 __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, int maxit, int* iters) {
     double r[4];
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
@@ -349,23 +438,14 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
         }
         if (!ok) { *iters = 0; return ST_UNPHYS; }
     }
-    double last_rel = 1e300;
+    double J[4][4];
+    int piv[4];
+    if (!rec_jacobian(k, x, J, piv, r)) { *iters = 0; return ST_NOCONV; }
+    bool fresh = true;
+    double last_rel = 1e300, prev_step = 1e300;
     for (int it = 1; it <= maxit; ++it) {
-        D4 xd[4], rd[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            xd[a] = mk(x[a]);
-            xd[a].d[a] = 1.0;
-        }
-        if (!rec_residual<D4>(k, xd, rd, nullptr)) { *iters = it; return ST_UNPHYS; }
-        double J[4][4], dx[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            dx[a] = -rd[a].v;
-#pragma unroll
-            for (int b = 0; b < 4; ++b) J[a][b] = rd[a].d[b];
-        }
-        if (!solve4(J, dx)) { *iters = it; return ST_NOCONV; }
+        double dx[4] = {-r[0], -r[1], -r[2], -r[3]};
+        lu4_solve(J, piv, dx);
         const double m0 = rec_merit(r, x[0]);
         double t = 1.0, xt[4], rt[4];
         bool acc = false;
@@ -379,13 +459,26 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
             }
             t *= 0.5;
         }
-        if (!acc) { *iters = it; return ST_NOCONV; }
+        if (!acc) {
+            if (fresh) { *iters = it; return ST_NOCONV; }
+            if (!rec_jacobian(k, x, J, piv, r)) { *iters = it; return ST_NOCONV; }
+            fresh = true;
+            continue;
+        }
         const double dp = fabs(xt[0] - x[0]);
         const double dv = fmax(fabs(xt[1] - x[1]), fmax(fabs(xt[2] - x[2]), fabs(xt[3] - x[3])));
 #pragma unroll
         for (int a = 0; a < 4; ++a) { x[a] = xt[a]; r[a] = rt[a]; }
         last_rel = dp / x[0];
         if (dp <= tol * x[0] && dv <= tol) { *iters = it; return ST_OK; }
+        const double step = fmax(last_rel, dv);
+        if (t < 1.0 || step > 0.25 * prev_step) {
+            if (!rec_jacobian(k, x, J, piv, r)) { *iters = it; return ST_NOCONV; }
+            fresh = true;
+        } else {
+            fresh = false;
+        }
+        prev_step = step;
     }
     *iters = maxit;
     return last_rel <= 1e-12 ? ST_WARN : ST_NOCONV;
@@ -408,15 +501,18 @@ __device__ int recover_plain(const RecIn& k, const double* Ec, double* x, double
     double p = x[0];
     double last_rel = 1e300;
     const double G = k.G;
+    const double iD = 1.0 / k.D;
     for (int it = 1; it <= maxit; ++it) {
         const double den = base + k.sg * p;
-        const double iden = 1.0 / den;
+        if (!(den > 0.0)) { *iters = it; return ST_UNPHYS; }
+        const double iden = frcp(den);
         const double w2 = s2 * iden * iden;
         if (!(w2 < 1.0) || !isfinite(w2)) { *iters = it; return ST_UNPHYS; }
-        const double Wn2 = 1.0 / (1.0 - w2);
-        const double Wn = sqrt(Wn2);
-        const double rho = k.D * k.isg / Wn;
-        const double eps = (k.tau - k.D * (Wn - 1.0) - k.sg * p * (Wn2 - 1.0) - em) / (k.D * Wn);
+        const double Wn = frsqrt(1.0 - w2);
+        const double Wn2 = Wn * Wn;
+        const double iW = frcp(Wn);
+        const double rho = k.D * k.isg * iW;
+        const double eps = (k.tau - k.D * (Wn - 1.0) - k.sg * p * (Wn2 - 1.0) - em) * (iW * iD);
         const double f = (G - 1.0) * rho * eps - p;
         const double cs2 = G * (G - 1.0) * eps / (1.0 + G * eps);
         const double pn = p - f / (w2 * cs2 - 1.0);
