@@ -63,6 +63,8 @@ def parse():
     ap.add_argument("--cpu-sample", default="96,96,48", help="oracle sub-box (nx,ny,nz) for cpu_baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also launch a plain device copy of known size (for HBM counter calibration)")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 stencil) form")
+    ap.add_argument("--mixed-steps", type=int, default=50, help="steps of the FP64-vs-mixed accuracy run")
     return ap.parse_args()
 
 
@@ -121,54 +123,66 @@ def main():
     t0 = time.perf_counter()
     w = W.curved_blob(n=args.n, recon=args.recon)
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s: {w.name}, padded {w.padded}")
-    g = rmhd.grid_for(w)
     met = torch.from_numpy(w.metric).cuda()
-    g.set_metric(met)
     sig = torch.from_numpy(w.sigma).cuda()
-    P = torch.from_numpy(w.P).cuda()
-    U = g.prim2con(P)
+    ncell = w.n_interior
 
+    def setup(precision):
+        g = rmhd.grid_for(w, precision=precision)
+        g.set_metric(met)
+        P = torch.from_numpy(w.P).cuda()
+        U = g.prim2con(P)
+        return g, U, P
+
+    g, U, P = setup("fp64")
     # CFL time step from the characteristic speeds (static metric: constant)
     smax = g.max_signal_speed()
     dt = 0.25 / smax
     log(f"max signal speed {smax:.6g} -> dt {dt:.6g} (CFL 0.25)")
 
-    t0 = time.perf_counter()
-    for _ in range(args.evolve):
-        g.step(dt, sig, U, P)
-    torch.cuda.synchronize()
-    nfail = g.failures()
-    log(f"{args.evolve} steps in {time.perf_counter() - t0:.2f} s, failed recoveries {nfail}")
-    if nfail:
-        raise SystemExit("recovery failures during evolution")
+    def evolve(g, U, P, steps, tag):
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            g.step(dt, sig, U, P)
+        torch.cuda.synchronize()
+        nfail = g.failures()
+        log(f"{tag}: {steps} steps in {time.perf_counter() - t0:.2f} s, failed recoveries {nfail}")
+        if nfail:
+            raise SystemExit("recovery failures during evolution")
 
-    # stage-2 inputs at this state
-    P1, R1 = g.empty(), g.empty(3)
-    g.imex_stage(1, dt, sig, U, P, P1, R_out=R1)
-    U2, P2, R2 = g.empty(), g.empty(), g.empty(3)
-
-    def stage2():
-        g.imex_stage(2, dt, sig, U, P1, P2, R_out=R2, R1=R1, U_out=U2)
-
-    for _ in range(args.warmup):
-        stage2()
-    torch.cuda.synchronize()
-    g.timing(True)
-    g.timing_read()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.steps):
-        stage2()
-    stop.record()
-    torch.cuda.synchronize()
-    ms = start.elapsed_time(stop)
-    kern = g.timing_read()
-    g.timing(False)
-    nfail = g.failures()
-    if nfail:
-        raise SystemExit(f"{nfail} failed recoveries in the timed stages")
-    ncell = w.n_interior
+
+    def time_stage2(g, U, P, steps, warmup):
+        """K timed applications of IMEX stage 2 at the state (U, P)"""
+        P1, R1 = g.empty(), g.empty(3)
+        g.imex_stage(1, dt, sig, U, P, P1, R_out=R1)
+        U2, P2, R2 = g.empty(), g.empty(), g.empty(3)
+
+        def stage2():
+            g.imex_stage(2, dt, sig, U, P1, P2, R_out=R2, R1=R1, U_out=U2)
+
+        for _ in range(warmup):
+            stage2()
+        torch.cuda.synchronize()
+        g.timing(True)
+        g.timing_read()
+        torch.cuda.synchronize()
+        start.record()
+        for _ in range(steps):
+            stage2()
+        stop.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(stop)
+        kern = g.timing_read()
+        g.timing(False)
+        nfail = g.failures()
+        if nfail:
+            raise SystemExit(f"{nfail} failed recoveries in the timed stages")
+        del P1, R1, U2, P2, R2
+        return ms, kern
+
+    evolve(g, U, P, args.evolve, "fp64")
+    ms, kern = time_stage2(g, U, P, args.steps, args.warmup)
     value = ncell * args.steps / (ms * 1e-3)
     log(f"stage 2: {ms / args.steps:.3f} ms -> {value:.4g} zone-updates/s")
 
@@ -192,6 +206,42 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    mixed = None
+    if not args.no_mixed:
+        gm, Um, Pm = setup("mixed")
+        evolve(gm, Um, Pm, args.evolve, "mixed")
+        ms_m, kern_m = time_stage2(gm, Um, Pm, args.steps, args.warmup)
+        val_m = ncell * args.steps / (ms_m * 1e-3)
+        log(f"mixed stage 2: {ms_m / args.steps:.3f} ms -> {val_m:.4g} zone-updates/s")
+        # accuracy: both forms from the same seed to the same step count
+        rest = max(0, args.mixed_steps - args.evolve)
+        evolve(g, U, P, rest, "fp64 accuracy run")
+        evolve(gm, Um, Pm, rest, "mixed accuracy run")
+        I = (slice(None),) + tuple(w.interior)
+        names = ["rho", "p", "vx", "vy", "vz", "Bx", "By", "Bz", "Ex", "Ey", "Ez", "phi", "psi", "q"]
+        errs = {}
+        # E (slaved to -v x B in the stiff interior) is measured against the
+        # electromagnetic scale max(|E|, |B|), as are phi, psi and q
+        em_max = float(P[5:11][I].abs().max())
+        em_sum = max(float(P[f][I[1:]].abs().sum()) for f in range(5, 11))
+        for f, nm in enumerate(names):
+            a, b = P[f][I[1:]], Pm[f][I[1:]]
+            d = (a - b).abs()
+            s1, si = float(a.abs().sum()), float(a.abs().max())
+            if f >= 8:
+                s1, si = max(s1, em_sum), max(si, em_max)
+            errs[nm] = {"L1": float(d.sum()) / max(s1, 1e-300), "Linf": float(d.max()) / max(si, 1e-300)}
+        worst = max(max(errs[n]["L1"], errs[n]["Linf"]) for n in ["rho", "p", "Bx", "By", "Bz", "Ex", "Ey", "Ez"])
+        mixed = {"value": val_m, "unit": "zone-updates/s", "ms_per_step": ms_m / args.steps,
+                 "speedup_vs_fp64": ms / ms_m,
+                 "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern_m.items()},
+                 "accuracy_steps": args.evolve + rest,
+                 "max_rel_err_rho_p_B_E": worst, "per_field_vs_fp64": errs,
+                 "reference": "the FP64 GPU path from the same seed (equal to the oracle by the parity tests)"}
+        log(f"mixed: speedup {ms / ms_m:.3f}, max rel err (rho, p, B, E) after {args.evolve + rest} steps "
+            f"{worst:.3e}")
+        del gm, Um, Pm
+
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
     dominant = max(per_launch, key=lambda k: kern[k][0])
     dom_ms = per_launch[dominant]
@@ -210,7 +260,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        del U, P, U2, P2, P1, R1, R2, Uc, Pc
+        del U, P, Uc, Pc
         t0 = time.perf_counter()
         cpu = cpu_baseline(w, dt, tuple(int(x) for x in args.cpu_sample.split(",")))
         log(f"cpu baseline {cpu['value']:.4g} zone-updates/s in {time.perf_counter() - t0:.1f} s")
@@ -236,6 +286,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels_ms_per_launch": per_launch,
         "full_step": {"ms": ms_step, "zone_updates_per_s_per_stage": 2 * ncell / (ms_step * 1e-3)},
+        "mixed": mixed,
     }
     print(json.dumps(out))
     return 0

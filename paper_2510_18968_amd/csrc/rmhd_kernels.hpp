@@ -100,10 +100,10 @@ __device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, cons
 // Loads are software-pipelined one field ahead and a scheduling barrier per
 // field stops the compiler from hoisting all 70 stencil loads (which would
 // need ~140 extra VGPRs and cut occupancy to one wave per SIMD).  The cell
-// values of v, B, E and q are kept for the cell-centre current.
+// values are kept in FP64 for the cell-centre current.
 template <int RECON, class R>
 __device__ __forceinline__ void recon_cell14(const double* __restrict__ P, long Np, long o, long s, R* fm, R* fp,
-                                             R* Pc) {
+                                             double* Pc) {
     double cur[5], nxt[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) cur[q] = P[o + (q - 2) * s];
@@ -115,7 +115,7 @@ __device__ __forceinline__ void recon_cell14(const double* __restrict__ P, long 
         }
         const R st[5] = {R(cur[0]), R(cur[1]), R(cur[2]), R(cur[3]), R(cur[4])};
         recon<RECON>(st, fm[f], fp[f]);
-        Pc[f] = st[2];
+        Pc[f] = cur[2];
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < 5; ++q) cur[q] = nxt[q];
@@ -145,22 +145,24 @@ __global__ __launch_bounds__(256) void k_flux_x(const Params p, const double* __
     const long o = ((long)k * p.np[1] + j) * p.np[0] + ic;
     const long Np = p.Np;
 
-    R fm[NF], fp[NF], Pc[NF];
+    R fm[NF], fp[NF];
+    double Pc[NF];
     recon_cell14<RECON>(P, Np, o, 1, fm, fp, Pc);
-    // cell-centre current, x component (charge flux at faces = mean of the two cells)
-    Geo<R> mc;
+    // cell-centre current, x component (charge flux at faces = mean of the two
+    // cells); FP64 in every form: sigma multiplies a near-cancelling bracket
+    Geo<double> mc;
     if (CURVED) {
-        mc.alp = R(1);
-        mc.bet[0] = mc.bet[1] = mc.bet[2] = R(0);
-        for (int a = 0; a < 6; ++a) mc.g[a] = R(p.gam[a * Np + o]);
+        mc.alp = 1.0;
+        mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
+        for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
         geo_finish(mc);
     } else {
         geo_flat(mc);
     }
     const long os = o - ic + bc_map(p, 0, ic);
-    R J[3];
-    current(mc, Pc, R(sig[os]), J);
-    const R JR = __shfl_down(J[0], 1);
+    double J[3];
+    current(mc, Pc, sig[os], J);
+    const double JR = __shfl_down(J[0], 1);
     R PR[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) PR[f] = __shfl_down(fm[f], 1);
@@ -173,7 +175,7 @@ __global__ __launch_bounds__(256) void k_flux_x(const Params p, const double* __
     if (bad_state(m, PR))
         for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + o + 1]);
     R Fh[NF];
-    face_flux<0>(p, m, fp, PR, R(0.5) * (J[0] + JR), Fh);
+    face_flux<0>(p, m, fp, PR, R(0.5 * (J[0] + JR)), Fh);
 
     const bool cell = lane >= 1 && lane <= XSEG && i >= p.g[0] && i < ilast;
     const R ih = R(p.idx[0]);
@@ -200,25 +202,27 @@ __global__ __launch_bounds__(64) void k_flux_march(const Params p, const double*
     const long base = (long)(i + p.g[0]) + (long)e * p.st[E];
     const R ih = R(p.idx[D]);
 
-    R PLc[NF], Fprev[NF], Jprev = R(0);
+    R PLc[NF], Fprev[NF];
+    double Jprev = 0.0;
 #pragma unroll 1
     for (int c = c0 - 1; c <= c1; ++c) {
         const int cp = c + p.g[D];
         const long o = base + (long)cp * s;
-        R fm[NF], fp[NF], Pc[NF];
+        R fm[NF], fp[NF];
+        double Pc[NF];
         recon_cell14<RECON>(P, Np, o, s, fm, fp, Pc);
-        Geo<R> mc;
+        Geo<double> mc;
         if (CURVED) {
-            mc.alp = R(1);
-            mc.bet[0] = mc.bet[1] = mc.bet[2] = R(0);
-            for (int a = 0; a < 6; ++a) mc.g[a] = R(p.gam[a * Np + o]);
+            mc.alp = 1.0;
+            mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
+            for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
             geo_finish(mc);
         } else {
             geo_flat(mc);
         }
         const long os = o + (long)(bc_map(p, D, cp) - cp) * s;
-        R J[3];
-        current(mc, Pc, R(sig[os]), J);
+        double J[3];
+        current(mc, Pc, sig[os], J);
         if (c >= c0) {
             // face between c - 1 and c
             Geo<R> m;
@@ -228,7 +232,7 @@ __global__ __launch_bounds__(64) void k_flux_march(const Params p, const double*
             if (bad_state(m, fm))
                 for (int f = 0; f < NF; ++f) fm[f] = R(P[f * Np + o]);
             R Fh[NF];
-            face_flux<D>(p, m, PLc, fm, R(0.5) * (Jprev + J[D]), Fh);
+            face_flux<D>(p, m, PLc, fm, R(0.5 * (Jprev + J[D])), Fh);
             if (c > c0) {
                 const long oc = o - s;
 #pragma unroll
