@@ -65,6 +65,8 @@ def parse():
                     help="also launch a plain device copy of known size (for HBM counter calibration)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 stencil) form")
     ap.add_argument("--mixed-steps", type=int, default=50, help="steps of the FP64-vs-mixed accuracy run")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint rollout timing")
+    ap.add_argument("--adjoint-steps", type=int, default=200, help="steps of the differentiated rollout")
     return ap.parse_args()
 
 
@@ -102,6 +104,45 @@ def cpu_baseline(w, dt, sample):
             "sample": f"one IMEX stage 2 on the central {nx}x{ny}x{nz} cells of the 256^3 curved-blob "
                       f"workload (real neighbour ghosts, held fixed), after two oracle steps; "
                       f"{t:.2f} s, {int(s2['nfail'])} failed cells"}
+
+
+def adjoint_leg(torch, rmhd, W, steps):
+    """Forward + adjoint of the 64 x 2048 current-sheet batch inverse problem
+    (200 steps, checkpoints every 20): one loss and gradient in (B^y_0,
+    log sigma) per timed pass; reported as seconds per IMEX step."""
+    from paper_2510_18968_amd.autograd import SheetInversion
+    w = W.sheet_batch(steps=steps)
+    g = rmhd.grid_for(w)
+    prob = SheetInversion(w, g, ckpt=20)
+    By0 = prob.P0[6].clone().requires_grad_(True)
+    ls = torch.tensor(w.extra["sigma_problem"], device="cuda").log().requires_grad_(True)
+
+    def fwd():
+        with torch.no_grad():
+            return prob.loss(By0, ls)
+
+    def fwd_bwd():
+        L = prob.loss(By0, ls)
+        return torch.autograd.grad(L, (By0, ls))
+
+    fwd_bwd()   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L = fwd()
+    torch.cuda.synchronize()
+    t_f = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    gB, gs = fwd_bwd()
+    torch.cuda.synchronize()
+    t_fb = time.perf_counter() - t0
+    if g.failures():
+        raise SystemExit("recovery failures in the adjoint rollout")
+    log(f"adjoint rollout {w.name}: forward {t_f:.3f} s, forward + adjoint {t_fb:.3f} s for {steps} steps")
+    return {"workload": f"{w.name}: {steps} IMEX steps, WENO5, loss sum (B^y(T) - target)^2, gradient in "
+                        f"(B^y_0, log sigma per problem), checkpoints every 20 steps",
+            "fwd_adjoint_s_per_step": t_fb / steps, "fwd_s_per_step": t_f / steps,
+            "adjoint_over_forward": (t_fb - t_f) / t_f, "loss": float(L),
+            "grad_norm_By0": float(gB.norm()), "grad_norm_log_sigma": float(gs.norm())}
 
 
 def main():
@@ -242,6 +283,10 @@ def main():
             f"{worst:.3e}")
         del gm, Um, Pm
 
+    adjoint = None
+    if not args.no_adjoint:
+        adjoint = adjoint_leg(torch, rmhd, W, args.adjoint_steps)
+
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
     dominant = max(per_launch, key=lambda k: kern[k][0])
     dom_ms = per_launch[dominant]
@@ -287,6 +332,7 @@ def main():
         "kernels_ms_per_launch": per_launch,
         "full_step": {"ms": ms_step, "zone_updates_per_s_per_stage": 2 * ncell / (ms_step * 1e-3)},
         "mixed": mixed,
+        "adjoint": adjoint,
     }
     print(json.dumps(out))
     return 0

@@ -143,6 +143,28 @@ int rmhd_imex_stage(rmhd_ctx* ctx, int stage, double dt, const double* sigma, co
  * buffers live in the workspace. */
 int rmhd_step(rmhd_ctx* ctx, double dt, const double* sigma, double* U, double* P);
 
+/* Bytes of caller-provided device scratch rmhd_step_adjoint needs (79 padded
+ * fields: adjoint buffers and per-face sensitivities). */
+size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc);
+
+/* Adjoint (reverse mode) of rmhd_step: given Ubar_np1 = dL/dU^{n+1}, writes
+ * Ubar_n = dL/dU^n (interior cells) and ADDS dL/dsigma to sigma_bar [Np]
+ * (interior cells).  U_n, P_n: the state the forward step started from (P_n
+ * is only the recovery guess; the recovered roots do not depend on it).  The
+ * forward stages are recomputed inside.  Differentiates the FP64 form: the
+ * recovery roots by the implicit-function theorem (Sec. III.B, eq. 3D_NR),
+ * the flux divergence and sources (eq. GRRMHD_flux_form) and reconstruction by
+ * their local Jacobians, the stage combination of eq. IMEX3 exactly; limiter
+ * kinks and first-order fallbacks take the derivative of the branch taken.
+ * Ubar_n may alias Ubar_np1.  adj_ws: >= rmhd_adjoint_workspace_bytes bytes,
+ * 256-byte aligned.  Returns RMHD_EINVAL for the mixed-precision form. */
+int rmhd_step_adjoint(rmhd_ctx* ctx, double dt, const double* sigma, const double* U_n, const double* P_n,
+                      const double* Ubar_np1, double* Ubar_n, double* sigma_bar, void* adj_ws, size_t adj_bytes);
+
+/* Adjoint of rmhd_prim2con at the primitives P: Pbar = (dU/dP)^T Ubar at
+ * interior cells (eqs. conserved_dens, conserved_tau, conserved_S). */
+int rmhd_prim2con_adjoint(rmhd_ctx* ctx, const double* P, const double* Ubar, double* Pbar);
+
 /* max over interior cells and active d of max|lambda^d_+-| / dx_d with the
  * characteristic speeds of Sec. III; a stable step is dt = CFL / value.
  * Synchronises the stream and writes *host_out. */

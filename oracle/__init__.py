@@ -76,6 +76,7 @@ def lib():
             "orc_stage2": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]),
             "orc_final": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]),
             "orc_step": (C.c_long, [gp, dp, C.c_double, dp, dp, dp]),
+            "orc_step_tangent": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp]),
             "orc_max_signal_speed": (C.c_double, [gp, dp]),
             "orc_num_threads": (C.c_int, []),
         }
@@ -274,6 +275,15 @@ def final(g, dt, sigma, Un, F1, P2, R1, R2, metric=None):
 def step(g, dt, sigma, U, P, metric=None):
     """One IMEX-SSP2(2,2,2) step in place; returns the number of failed cells."""
     return lib().orc_step(C.byref(g), _p(metric), dt, _p(sigma), _p(U), _p(P))
+
+
+def step_tangent(g, dt, sigma, U, dU, P, dsigma=None, metric=None):
+    """One step in place on (U, P) in dual numbers: dU (in/out) is the
+    directional derivative of U along the input direction (dU, dsigma).
+    Returns (failed cells, dP)."""
+    dP = np.zeros_like(P)
+    nf = lib().orc_step_tangent(C.byref(g), _p(metric), dt, _p(sigma), _p(dsigma), _p(U), _p(dU), _p(P), _p(dP))
+    return nf, dP
 
 
 def max_signal_speed(g, metric=None):

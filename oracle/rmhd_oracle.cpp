@@ -39,7 +39,9 @@
  *     derivatives at centres by 4th-order central differences;
  *   - stiff terms of the final update recovered from the stage equations;
  *   - recovery stops when |dp| <= tol p and max|dv^i| <= tol;
- *   - a face state with rho<=0, p<=0 or v^2>=1 falls back to first order.
+ *   - a face state with rho<=0, p<=0 or v^2>=1 falls back to first order;
+ *   - derivatives through a limiter or a fallback are those of the branch
+ *     taken (at a tie or a zero slope the returned branch, not an average).
  *
  * Parity status: every function here is pinned by tests in tests/ against
  * closed forms, library routines, invariants or brute force, except the
@@ -408,8 +410,12 @@ void hlle(const T* UL, const T* UR, const T* FL, const T* FR, T lp, T lm, T* Fh)
 /* Reconstruction of one field from the 5-cell stencil f[0..4] = f_{i-2..i+2}*/
 /* to the faces i-1/2 (fm) and i+1/2 (fp).                                   */
 /* ------------------------------------------------------------------------ */
+/* minmod: zero unless both slopes share a strict sign, else the one of
+ * smaller magnitude (b on a tie).  Written as a branch so that a derivative
+ * taken through it is that of the returned branch, also at a zero slope. */
 template <class T> T minmod2(T a, T b) {
-    return 0.5 * (sgn(a) + sgn(b)) * tmin(fabs(a), fabs(b));
+    if (!(sgn(a) * sgn(b) > 0)) return T(0.0);
+    return std::fabs(val(a)) < std::fabs(val(b)) ? a : b;
 }
 template <class T> T minmod3(T a, T b, T c) {
     if (val(a) > 0 && val(b) > 0 && val(c) > 0) return tmin(a, tmin(b, c));
@@ -1298,6 +1304,44 @@ long orc_step(const Grid* gr, const double* metric, double dt, const double* sig
     std::vector<double> Un(U, U + n);
     nf += final_update(*gr, metric, dt, sig, Un.data(), F1.data(), P2.data(), R1.data(), R2.data(), U, P,
                        (int32_t*)nullptr, (int32_t*)nullptr);
+    return nf;
+}
+
+/* Tangent of one step (forward-mode dual numbers through every function
+ * above, recovery roots included): (U, P) advance in place, dU carries the
+ * directional derivative for the input direction (dU, dsigma).  dP, the
+ * derivative of the primitives, is written too. */
+long orc_step_tangent(const Grid* gr, const double* metric, double dt, const double* sig, const double* dsig,
+                      double* U, double* dU, double* P, double* dP) {
+    Geo ge(*gr);
+    const size_t n = (size_t)NF * ge.Np;
+    std::vector<Dual> Ud(n), Pd(n), sd(ge.Np), md;
+    for (size_t i = 0; i < n; ++i) {
+        Ud[i] = Dual(U[i], dU[i]);
+        Pd[i] = Dual(P[i], 0.0);
+    }
+    for (long i = 0; i < ge.Np; ++i) sd[i] = Dual(sig[i], dsig ? dsig[i] : 0.0);
+    const Dual* mp = nullptr;
+    if (metric) {
+        md.resize((size_t)NM * ge.Np);
+        for (size_t i = 0; i < md.size(); ++i) md[i] = Dual(metric[i]);
+        mp = md.data();
+    }
+    std::vector<Dual> P1(Pd), U1(Ud), R1((size_t)3 * ge.Np, Dual(0.0)), U2(Ud), P2(Pd), R2((size_t)3 * ge.Np, Dual(0.0)),
+        F1(n, Dual(0.0));
+    long nf = stage1(*gr, mp, dt, sd.data(), Ud.data(), Pd.data(), P1.data(), R1.data(), U1.data(), (int32_t*)nullptr,
+                     (int32_t*)nullptr);
+    nf += stage2(*gr, mp, dt, sd.data(), Ud.data(), P1.data(), R1.data(), U2.data(), P2.data(), R2.data(), F1.data(),
+                 (int32_t*)nullptr, (int32_t*)nullptr);
+    std::vector<Dual> Un(Ud);
+    nf += final_update(*gr, mp, dt, sd.data(), Un.data(), F1.data(), P2.data(), R1.data(), R2.data(), Ud.data(),
+                       Pd.data(), (int32_t*)nullptr, (int32_t*)nullptr);
+    for (size_t i = 0; i < n; ++i) {
+        U[i] = Ud[i].v;
+        dU[i] = Ud[i].d;
+        P[i] = Pd[i].v;
+        if (dP) dP[i] = Pd[i].d;
+    }
     return nf;
 }
 

@@ -9,7 +9,7 @@
 #include <vector>
 
 #include "rmhd.h"
-#include "rmhd_kernels.hpp"
+#include "rmhd_adjoint.hpp"
 
 using namespace rmhd;
 
@@ -225,9 +225,142 @@ int stage3(rmhd_ctx* c, double dt, const double* sig, const double* Un, const do
     return update<3>(c, dt, sig, Un, U2, P2, R1, R2, Uo, Po, nullptr, st);
 }
 
+constexpr int ADJ_FIELDS = 79;   // Ub2 14, Pb 14, Lb 14, R1b 3, R2b 3, sb 1, fb 30
+
+template <bool CURVED, int RECON> int adj_L_t(rmhd_ctx* c, const double* P, const double* sig, double* Lb,
+                                              double* Pb, double* sb, double* fb) {
+    const Params& p = c->p;
+    const long n = ncells(p);
+    k_adj_sources<CURVED><<<nblk(n, 256), 256, 0, c->stream>>>(p, P, Lb, Pb);
+    LAUNCH_CHECK();
+    for (int d = 0; d < 3; ++d) {
+        if (!is_active(p, d)) continue;
+        const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+        const long nf = (long)(p.n[d] + 1) * p.n[e1] * p.n[e2];
+        const long nc = (long)p.np[d] * p.n[e1] * p.n[e2];
+        if (d == 0) {
+            k_adj_face<0, RECON, CURVED><<<nblk(nf, 128), 128, 0, c->stream>>>(p, P, sig, Lb, fb);
+            LAUNCH_CHECK();
+            k_adj_cell<0, RECON, CURVED><<<nblk(nc, 128), 128, 0, c->stream>>>(p, P, sig, fb, Pb, sb);
+        } else if (d == 1) {
+            k_adj_face<1, RECON, CURVED><<<nblk(nf, 128), 128, 0, c->stream>>>(p, P, sig, Lb, fb);
+            LAUNCH_CHECK();
+            k_adj_cell<1, RECON, CURVED><<<nblk(nc, 128), 128, 0, c->stream>>>(p, P, sig, fb, Pb, sb);
+        } else {
+            k_adj_face<2, RECON, CURVED><<<nblk(nf, 128), 128, 0, c->stream>>>(p, P, sig, Lb, fb);
+            LAUNCH_CHECK();
+            k_adj_cell<2, RECON, CURVED><<<nblk(nc, 128), 128, 0, c->stream>>>(p, P, sig, fb, Pb, sb);
+        }
+        LAUNCH_CHECK();
+    }
+    for (int d = 0; d < 3; ++d) {
+        if (!is_active(p, d)) continue;
+        const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+        const long nt = 2L * p.n[e1] * p.n[e2];
+        k_adj_fold<<<nblk(nt, 256), 256, 0, c->stream>>>(p, Pb, NF, d);
+        LAUNCH_CHECK();
+        k_adj_fold<<<nblk(nt, 256), 256, 0, c->stream>>>(p, sb, 1, d);
+        LAUNCH_CHECK();
+    }
+    return RMHD_OK;
+}
+
+// adjoint of L(P) = -div F(P) + S(P): Pb += (dL/dP)^T Lb, sb += (dL/dsigma)^T Lb
+int adj_L(rmhd_ctx* c, const double* P, const double* sig, double* Lb, double* Pb, double* sb, double* fb) {
+    const int r = c->desc.recon;
+    if (c->curved) {
+        if (r == RMHD_RECON_MINMOD) return adj_L_t<true, REC_MINMOD>(c, P, sig, Lb, Pb, sb, fb);
+        if (r == RMHD_RECON_MC2) return adj_L_t<true, REC_MC2>(c, P, sig, Lb, Pb, sb, fb);
+        return adj_L_t<true, REC_WENO5>(c, P, sig, Lb, Pb, sb, fb);
+    }
+    if (r == RMHD_RECON_MINMOD) return adj_L_t<false, REC_MINMOD>(c, P, sig, Lb, Pb, sb, fb);
+    if (r == RMHD_RECON_MC2) return adj_L_t<false, REC_MC2>(c, P, sig, Lb, Pb, sb, fb);
+    return adj_L_t<false, REC_WENO5>(c, P, sig, Lb, Pb, sb, fb);
+}
+
+template <int STAGE>
+int adj_point(rmhd_ctx* c, double dt, const double* sig, const double* Us, const double* Rs, const double* Ps,
+              const double* Ubs, const double* Pb, const double* Rb, double* Ubn, double* Lb, double* R1b,
+              double* sb) {
+    const long n = ncells(c->p);
+    if (c->curved)
+        k_adj_point<STAGE, true><<<nblk(n, 128), 128, 0, c->stream>>>(c->p, dt, sig, Us, Rs, Ps, Ubs, Pb, Rb, Ubn,
+                                                                      Lb, R1b, sb);
+    else
+        k_adj_point<STAGE, false><<<nblk(n, 128), 128, 0, c->stream>>>(c->p, dt, sig, Us, Rs, Ps, Ubs, Pb, Rb, Ubn,
+                                                                       Lb, R1b, sb);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
+int fill(rmhd_ctx* c, double* a, long n) {
+    k_fill<<<(unsigned)std::min<long>(nblk(n, 256), 8192), 256, 0, c->stream>>>(a, n, 0.0);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
+
+size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc) {
+    std::string why;
+    if (!check_desc(desc, why)) {
+        g_err = why;
+        return 0;
+    }
+    return up((size_t)ADJ_FIELDS * (size_t)padded_cells(desc) * sizeof(double)) + ALIGN;
+}
+
+int rmhd_step_adjoint(rmhd_ctx* c, double dt, const double* sigma, const double* U_n, const double* P_n,
+                      const double* Ubar_np1, double* Ubar_n, double* sigma_bar, void* adj_ws, size_t adj_bytes) {
+    if (!c || !sigma || !U_n || !P_n || !Ubar_np1 || !Ubar_n || !sigma_bar || !adj_ws)
+        return fail(RMHD_EINVAL, "null argument");
+    if (!(dt > 0.0)) return fail(RMHD_EINVAL, "dt must be > 0");
+    if (c->desc.precision != RMHD_PREC_FP64) return fail(RMHD_EINVAL, "the adjoint differentiates the FP64 form");
+    if (adj_bytes < rmhd_adjoint_workspace_bytes(&c->desc)) return fail(RMHD_EINVAL, "adjoint workspace too small");
+    if ((reinterpret_cast<uintptr_t>(adj_ws) % ALIGN) != 0) return fail(RMHD_EINVAL, "adjoint workspace not aligned");
+    const long Np = c->p.Np;
+    double* base = static_cast<double*>(adj_ws);
+    double* Ub2 = base;
+    double* Pb = Ub2 + 14 * Np;
+    double* Lb = Pb + 14 * Np;
+    double* R1b = Lb + 14 * Np;
+    double* R2b = R1b + 3 * Np;
+    double* sb = R2b + 3 * Np;
+    double* fb = sb + Np;
+    int r;
+    // forward recompute of the stages
+    if ((r = stage1(c, dt, sigma, U_n, P_n, c->P1, c->R1, nullptr, nullptr)) != RMHD_OK) return r;
+    if ((r = stage2(c, dt, sigma, U_n, c->P1, c->R1, c->U2, c->P2, c->R2, nullptr)) != RMHD_OK) return r;
+    if ((r = ghost_fill(c, c->P2, NF)) != RMHD_OK) return r;
+    // reverse sweep
+    const long n = ncells(c->p);
+    k_adj_final<<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, Ubar_np1, Ubar_n, Ub2, Lb, R1b, R2b);
+    LAUNCH_CHECK();
+    if ((r = fill(c, Pb, 14 * Np)) != RMHD_OK) return r;
+    if ((r = fill(c, sb, Np)) != RMHD_OK) return r;
+    if ((r = adj_L(c, c->P2, sigma, Lb, Pb, sb, fb)) != RMHD_OK) return r;
+    if ((r = adj_point<2>(c, dt, sigma, c->U2, c->R2, c->P2, Ub2, Pb, R2b, Ubar_n, Lb, R1b, sb)) != RMHD_OK) return r;
+    if ((r = fill(c, Pb, 14 * Np)) != RMHD_OK) return r;
+    if ((r = adj_L(c, c->P1, sigma, Lb, Pb, sb, fb)) != RMHD_OK) return r;
+    if ((r = adj_point<1>(c, dt, sigma, U_n, nullptr, c->P1, nullptr, Pb, R1b, Ubar_n, nullptr, nullptr, sb)) !=
+        RMHD_OK)
+        return r;
+    k_adj_sigma_out<<<nblk(n, 256), 256, 0, c->stream>>>(c->p, sb, sigma_bar);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
+int rmhd_prim2con_adjoint(rmhd_ctx* c, const double* P, const double* Ubar, double* Pbar) {
+    if (!c || !P || !Ubar || !Pbar) return fail(RMHD_EINVAL, "null argument");
+    const long n = ncells(c->p);
+    if (c->curved) k_adj_prim2con<true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, P, Ubar, Pbar);
+    else k_adj_prim2con<false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, P, Ubar, Pbar);
+    LAUNCH_CHECK();
+    return RMHD_OK;
+}
+
 
 const char* rmhd_last_error(void) { return g_err.c_str(); }
 

@@ -371,31 +371,49 @@ __global__ __launch_bounds__(256) void k_con2prim(const Params p, const double* 
 }
 
 // ------------------------------------------------------- explicit sources
-// eq. GRRMHD_flux_form at a cell centre, E rows without R_E; metric
-// derivatives by 4th-order central differences along active dimensions
+// metric derivatives at a cell centre: 4th-order central differences along
+// active dimensions (zero along the others), and K_ij
+struct MetricDerivs {
+    double da[3], db[3][3], dg[3][6], K[6];
+};
+
 template <bool CURVED>
-__device__ __forceinline__ void sources(const Params& p, long o, const Geo<double>& m, const double* Pc,
-                                        const double* Uc, double* S) {
-    const double* v = Pc + I_V;
-    if (!CURVED) {
-        for (int f = 0; f < NF; ++f) S[f] = 0.0;
-        for (int i = 0; i < 3; ++i) S[I_E + i] = -Uc[I_Q] * v[i];
-        S[I_PHI] = -p.kappa * Uc[I_PHI];
-        S[I_PSI] = Uc[I_Q] - p.kappa * Uc[I_PSI];
-        return;
+__device__ __forceinline__ void metric_derivs(const Params& p, long o, MetricDerivs& md) {
+    for (int d = 0; d < 3; ++d) {
+        md.da[d] = 0.0;
+        for (int a = 0; a < 3; ++a) md.db[d][a] = 0.0;
+        for (int a = 0; a < 6; ++a) md.dg[d][a] = 0.0;
     }
-    double da[3] = {0, 0, 0}, db[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, dg[3][6];
-    for (int d = 0; d < 3; ++d)
-        for (int a = 0; a < 6; ++a) dg[d][a] = 0.0;
+    for (int a = 0; a < 6; ++a) md.K[a] = 0.0;
+    if (!CURVED) return;
     for (int d = 0; d < 3; ++d) {
         if (!is_active(p, d)) continue;
         const long s = p.st[d];
         const double c = p.idx[d] / 12.0;
         auto D4 = [&](const double* f) { return (f[o - 2 * s] - 8.0 * f[o - s] + 8.0 * f[o + s] - f[o + 2 * s]) * c; };
-        da[d] = D4(p.alp);
+        md.da[d] = D4(p.alp);
         if (p.bet)
-            for (int a = 0; a < 3; ++a) db[d][a] = D4(p.bet + a * p.Np);
-        for (int a = 0; a < 6; ++a) dg[d][a] = D4(p.gam + a * p.Np);
+            for (int a = 0; a < 3; ++a) md.db[d][a] = D4(p.bet + a * p.Np);
+        for (int a = 0; a < 6; ++a) md.dg[d][a] = D4(p.gam + a * p.Np);
+    }
+    if (p.K)
+        for (int a = 0; a < 6; ++a) md.K[a] = p.K[a * p.Np + o];
+}
+
+// eq. GRRMHD_flux_form sources at a cell centre, E rows without R_E.
+// R: double, or the dual type of the adjoint's tangent passes (the metric
+// is fixed input and enters as double)
+template <bool CURVED, class R>
+__device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m, const MetricDerivs& md,
+                                          const R* Pc, const R* Uc, R* S) {
+    const R* v = Pc + I_V;
+    const double kap = p.kappa;
+    if (!CURVED) {
+        for (int f = 0; f < NF; ++f) S[f] = R(0.0);
+        for (int i = 0; i < 3; ++i) S[I_E + i] = -(Uc[I_Q] * v[i]);
+        S[I_PHI] = -(Uc[I_PHI] * kap);
+        S[I_PSI] = Uc[I_Q] - Uc[I_PSI] * kap;
+        return;
     }
     const double a = m.alp;
     // Gamma^i = gamma^il (gamma^jk d_j gamma_lk - 1/2 gamma^jk d_l gamma_jk)
@@ -404,59 +422,71 @@ __device__ __forceinline__ void sources(const Params& p, long o, const Geo<doubl
         double s1 = 0.0, s2 = 0.0;
         for (int j = 0; j < 3; ++j)
             for (int kk = 0; kk < 3; ++kk) {
-                s1 += m.gi[sidx(j, kk)] * dg[j][sidx(l, kk)];
-                s2 += m.gi[sidx(j, kk)] * dg[l][sidx(j, kk)];
+                s1 += m.gi[sidx(j, kk)] * md.dg[j][sidx(l, kk)];
+                s2 += m.gi[sidx(j, kk)] * md.dg[l][sidx(j, kk)];
             }
         A[l] = s1 - 0.5 * s2;
     }
     for (int i = 0; i < 3; ++i) {
         Gm[i] = m.gi[sidx(i, 0)] * A[0] + m.gi[sidx(i, 1)] * A[1] + m.gi[sidx(i, 2)] * A[2];
-        gda[i] = m.gi[sidx(i, 0)] * da[0] + m.gi[sidx(i, 1)] * da[1] + m.gi[sidx(i, 2)] * da[2];
+        gda[i] = m.gi[sidx(i, 0)] * md.da[0] + m.gi[sidx(i, 1)] * md.da[1] + m.gi[sidx(i, 2)] * md.da[2];
     }
     // densitised stress with both indices up
-    const double* B = Pc + I_B;
-    const double* E = Pc + I_E;
-    double vl[3], Bl[3], El[3];
+    const R* B = Pc + I_B;
+    const R* E = Pc + I_E;
+    R vl[3], Bl[3], El[3];
     lower(m.g, v, vl);
     lower(m.g, B, Bl);
     lower(m.g, E, El);
-    const double W2 = 1.0 / (1.0 - dot3(vl, v));
-    const double hW2 = (Pc[I_RHO] + p.G / (p.G - 1.0) * Pc[I_P]) * W2;
-    const double pt = Pc[I_P] + 0.5 * (dot3(El, E) + dot3(Bl, B));
-    double Su[6];
+    const R W = frsqrt(R(1.0) - dot3(vl, v));
+    const R hW2 = (Pc[I_RHO] + Pc[I_P] * (p.G / (p.G - 1.0))) * (W * W);
+    const R pt = Pc[I_P] + (dot3(El, E) + dot3(Bl, B)) * 0.5;
+    R Su[6];
     for (int j = 0; j < 3; ++j)
         for (int kk = j; kk < 3; ++kk)
-            Su[sidx(j, kk)] = m.sg * (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk] + m.gi[sidx(j, kk)] * pt);
-    const double* Sl = Uc + I_S;
-    double Sup[3];
-    for (int i = 0; i < 3; ++i) Sup[i] = m.gi[sidx(i, 0)] * Sl[0] + m.gi[sidx(i, 1)] * Sl[1] + m.gi[sidx(i, 2)] * Sl[2];
-    double Ktr = 0.0, SK = 0.0;
+            Su[sidx(j, kk)] = (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk] + pt * m.gi[sidx(j, kk)]) * m.sg;
+    const R* Sl = Uc + I_S;
+    R Sup[3];
+    for (int i = 0; i < 3; ++i) Sup[i] = Sl[0] * m.gi[sidx(i, 0)] + Sl[1] * m.gi[sidx(i, 1)] + Sl[2] * m.gi[sidx(i, 2)];
+    double Ktr = 0.0;
+    R SK = R(0.0);
     if (p.K) {
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
-                const double kij = p.K[sidx(i, j) * p.Np + o];
+                const double kij = md.K[sidx(i, j)];
                 Ktr += m.gi[sidx(i, j)] * kij;
                 SK += Su[sidx(i, j)] * kij;
             }
     }
-    S[I_D] = 0.0;
+    S[I_D] = R(0.0);
     for (int i = 0; i < 3; ++i) {
-        double t = 0.0;
+        R t = R(0.0);
         for (int j = 0; j < 3; ++j)
-            for (int kk = 0; kk < 3; ++kk) t += Su[sidx(j, kk)] * dg[i][sidx(j, kk)];
-        S[I_S + i] = 0.5 * a * t + (Sl[0] * db[i][0] + Sl[1] * db[i][1] + Sl[2] * db[i][2]) -
-                     (Uc[I_TAU] + Uc[I_D]) * da[i];
+            for (int kk = 0; kk < 3; ++kk) t += Su[sidx(j, kk)] * md.dg[i][sidx(j, kk)];
+        S[I_S + i] = t * (0.5 * a) + (Sl[0] * md.db[i][0] + Sl[1] * md.db[i][1] + Sl[2] * md.db[i][2]) -
+                     (Uc[I_TAU] + Uc[I_D]) * md.da[i];
     }
-    S[I_TAU] = a * SK - dot3(Sup, da);
+    S[I_TAU] = SK * a - (Sup[0] * md.da[0] + Sup[1] * md.da[1] + Sup[2] * md.da[2]);
     for (int i = 0; i < 3; ++i) {
-        const double bb = Uc[I_B] * db[0][i] + Uc[I_B + 1] * db[1][i] + Uc[I_B + 2] * db[2][i];
-        const double eb = Uc[I_E] * db[0][i] + Uc[I_E + 1] * db[1][i] + Uc[I_E + 2] * db[2][i];
-        S[I_B + i] = -bb + Uc[I_PHI] * (gda[i] - a * Gm[i]);
-        S[I_E + i] = -eb + Uc[I_PSI] * (gda[i] - a * Gm[i]) - a * Uc[I_Q] * v[i];
+        const R bb = Uc[I_B] * md.db[0][i] + Uc[I_B + 1] * md.db[1][i] + Uc[I_B + 2] * md.db[2][i];
+        const R eb = Uc[I_E] * md.db[0][i] + Uc[I_E + 1] * md.db[1][i] + Uc[I_E + 2] * md.db[2][i];
+        const double gg = gda[i] - a * Gm[i];
+        S[I_B + i] = Uc[I_PHI] * gg - bb;
+        S[I_E + i] = Uc[I_PSI] * gg - eb - Uc[I_Q] * v[i] * a;
     }
-    S[I_PHI] = -a * Uc[I_PHI] * Ktr + dot3(Uc + I_B, da) - a * p.kappa * Uc[I_PHI];
-    S[I_PSI] = -a * Uc[I_PSI] * Ktr + dot3(Uc + I_E, da) + a * Uc[I_Q] - a * p.kappa * Uc[I_PSI];
-    S[I_Q] = 0.0;
+    S[I_PHI] = -(Uc[I_PHI] * (a * Ktr)) + (Uc[I_B] * md.da[0] + Uc[I_B + 1] * md.da[1] + Uc[I_B + 2] * md.da[2]) -
+               Uc[I_PHI] * (a * kap);
+    S[I_PSI] = -(Uc[I_PSI] * (a * Ktr)) + (Uc[I_E] * md.da[0] + Uc[I_E + 1] * md.da[1] + Uc[I_E + 2] * md.da[2]) +
+               Uc[I_Q] * a - Uc[I_PSI] * (a * kap);
+    S[I_Q] = R(0.0);
+}
+
+template <bool CURVED>
+__device__ __forceinline__ void sources(const Params& p, long o, const Geo<double>& m, const double* Pc,
+                                        const double* Uc, double* S) {
+    MetricDerivs md;
+    metric_derivs<CURVED>(p, o, md);
+    sources_t<CURVED, double>(p, m, md, Pc, Uc, S);
 }
 
 // --------------------------------------------------------------- stages

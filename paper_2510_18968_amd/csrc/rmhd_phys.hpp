@@ -14,6 +14,9 @@
 namespace rmhd {
 
 using ::sqrt;
+using ::fabs;
+using ::fmin;
+using ::fmax;
 
 // FP64 reciprocal / reciprocal square root: hardware estimate refined by two
 // Newton steps (about 1 ulp; no IEEE scaling or fix-up, so arguments must be
@@ -77,7 +80,7 @@ template <class R> __device__ __forceinline__ void geo_finish(Geo<R>& m) {
     m.isg = rs;
 }
 
-template <class R> __device__ __forceinline__ void lower(const R* g, const R* u, R* l) {
+template <class M, class R> __device__ __forceinline__ void lower(const M* g, const R* u, R* l) {
     l[0] = g[0] * u[0] + g[1] * u[1] + g[2] * u[2];
     l[1] = g[1] * u[0] + g[3] * u[1] + g[4] * u[2];
     l[2] = g[2] * u[0] + g[4] * u[1] + g[5] * u[2];
@@ -93,7 +96,7 @@ template <class R> __device__ __forceinline__ void cross(const R* a, const R* b,
 }
 
 // ---------------------------------------------------------------- prim2con
-template <class R> __device__ __forceinline__ void prim2con(const Geo<R>& m, R G, const R* P, R* U) {
+template <class M, class R> __device__ __forceinline__ void prim2con(const Geo<M>& m, R G, const R* P, R* U) {
     const R* v = P + I_V;
     const R* B = P + I_B;
     const R* E = P + I_E;
@@ -106,33 +109,33 @@ template <class R> __device__ __forceinline__ void prim2con(const Geo<R>& m, R G
     const R hW2 = (P[I_RHO] + G / (G - R(1)) * P[I_P]) * W2;
     const R em = R(0.5) * (dot3(El, E) + dot3(Bl, B));
     cross(E, B, c);   // eta_ijk E^j B^k; epsilon_ijk = sqrt(gamma) eta_ijk
-    const R D = m.sg * P[I_RHO] * W;
+    const R D = P[I_RHO] * W * m.sg;
     U[I_D] = D;
-    for (int i = 0; i < 3; ++i) U[I_S + i] = m.sg * (hW2 * vl[i] + m.sg * c[i]);
-    U[I_TAU] = m.sg * (hW2 - P[I_P] + em) - D;
-    for (int a = I_B; a < NF; ++a) U[a] = m.sg * P[a];
+    for (int i = 0; i < 3; ++i) U[I_S + i] = (hW2 * vl[i] + c[i] * m.sg) * m.sg;
+    U[I_TAU] = (hW2 - P[I_P] + em) * m.sg - D;
+    for (int a = I_B; a < NF; ++a) U[a] = P[a] * m.sg;
 }
 
 // densitised current of eq. Ohm_law at a point:
 // J^i = Q v^i + W sigma [Ecal^i + (v_l x B_l)^i - (v_l . Ecal) v^i]
-template <class R> __device__ __forceinline__ void current(const Geo<R>& m, const R* P, R sigma, R* J) {
+template <class M, class R> __device__ __forceinline__ void current(const Geo<M>& m, const R* P, R sigma, R* J) {
     const R* v = P + I_V;
     R vl[3], Bl[3], vb[3];
     lower(m.g, v, vl);
     lower(m.g, P + I_B, Bl);
     cross(vl, Bl, vb);
     const R W = frsqrt(R(1) - dot3(vl, v));
-    const R Ec[3] = {m.sg * P[I_E], m.sg * P[I_E + 1], m.sg * P[I_E + 2]};
+    const R Ec[3] = {P[I_E] * m.sg, P[I_E + 1] * m.sg, P[I_E + 2] * m.sg};
     const R vE = dot3(vl, Ec);
-    const R Q = m.sg * P[I_Q];
+    const R Q = P[I_Q] * m.sg;
     for (int i = 0; i < 3; ++i) J[i] = Q * v[i] + W * sigma * (Ec[i] + vb[i] - vE * v[i]);
 }
 
 // conserved variables and physical flux along D of one state (eqs.
 // conserved_*, GRRMHD_flux_form with sqrt(gamma) counted once); Jd is the
 // current carried by the charge flux at this face
-template <int D, class R>
-__device__ __forceinline__ void state_flux(const Geo<R>& m, R G, const R* P, R Jd, R* U, R* F) {
+template <int D, class M, class R>
+__device__ __forceinline__ void state_flux(const Geo<M>& m, R G, const R* P, R Jd, R* U, R* F) {
     const R* v = P + I_V;
     const R* B = P + I_B;
     const R* E = P + I_E;
@@ -145,18 +148,18 @@ __device__ __forceinline__ void state_flux(const Geo<R>& m, R G, const R* P, R J
     const R em = R(0.5) * (dot3(El, E) + dot3(Bl, B));
     const R pt = P[I_P] + em;
     cross(E, B, c);
-    const R sg = m.sg;
-    const R Dd = sg * P[I_RHO] * W;
+    const M sg = m.sg;
+    const R Dd = P[I_RHO] * W * sg;
     U[I_D] = Dd;
-    for (int i = 0; i < 3; ++i) U[I_S + i] = sg * (hW2 * vl[i] + sg * c[i]);
-    U[I_TAU] = sg * (hW2 - P[I_P] + em) - Dd;
-    for (int a = I_B; a < NF; ++a) U[a] = sg * P[a];
-    const R a = m.alp, bd = m.bet[D], as = m.alp * sg;
+    for (int i = 0; i < 3; ++i) U[I_S + i] = (hW2 * vl[i] + c[i] * sg) * sg;
+    U[I_TAU] = (hW2 - P[I_P] + em) * sg - Dd;
+    for (int a = I_B; a < NF; ++a) U[a] = P[a] * sg;
+    const M a = m.alp, bd = m.bet[D], as = m.alp * sg;
     const R vd = v[D], Ed = E[D], Bd = B[D];
     F[I_D] = (a * vd - bd) * Dd;
     for (int i = 0; i < 3; ++i)
         F[I_S + i] = as * (hW2 * vd * vl[i] - Ed * El[i] - Bd * Bl[i] + (i == D ? pt : R(0))) - bd * U[I_S + i];
-    const R Sd = m.gi[sidx(D, 0)] * U[I_S] + m.gi[sidx(D, 1)] * U[I_S + 1] + m.gi[sidx(D, 2)] * U[I_S + 2];
+    const R Sd = U[I_S] * m.gi[sidx(D, 0)] + U[I_S + 1] * m.gi[sidx(D, 1)] + U[I_S + 2] * m.gi[sidx(D, 2)];
     F[I_TAU] = a * (Sd - vd * Dd) - bd * U[I_TAU];
     // (e_D x X)^i for covariant X
     R eE[3], eB[3];
@@ -164,7 +167,7 @@ __device__ __forceinline__ void state_flux(const Geo<R>& m, R G, const R* P, R J
     if (D == 1) { eE[0] = El[2]; eE[1] = R(0); eE[2] = -El[0]; eB[0] = Bl[2]; eB[1] = R(0); eB[2] = -Bl[0]; }
     if (D == 2) { eE[0] = -El[1]; eE[1] = El[0]; eE[2] = R(0); eB[0] = -Bl[1]; eB[1] = Bl[0]; eB[2] = R(0); }
     for (int i = 0; i < 3; ++i) {
-        const R gid = m.gi[sidx(i, D)];
+        const M gid = m.gi[sidx(i, D)];
         F[I_B + i] = a * (eE[i] + gid * U[I_PHI]) - bd * U[I_B + i];
         F[I_E + i] = -a * (eB[i] - gid * U[I_PSI]) - bd * U[I_E + i];
     }
@@ -265,9 +268,13 @@ __device__ __forceinline__ double val(double x) { return x; }
 __device__ __forceinline__ double val(const D4& x) { return x.v; }
 
 // one-direction dual number (value, derivative): Jacobian columns one at a
-// time keep 2 doubles per intermediate instead of 5
+// time keep 2 doubles per intermediate instead of 5; also the scalar type of
+// the tangent passes of the adjoint
 struct D1 {
     double v, d;
+    D1() = default;
+    __host__ __device__ constexpr explicit D1(double x) : v(x), d(0.0) {}
+    __host__ __device__ constexpr D1(double x, double dx) : v(x), d(dx) {}
 };
 __device__ __forceinline__ D1 operator+(const D1& a, const D1& b) { return D1{a.v + b.v, a.d + b.d}; }
 __device__ __forceinline__ D1 operator-(const D1& a, const D1& b) { return D1{a.v - b.v, a.d - b.d}; }
@@ -279,6 +286,9 @@ __device__ __forceinline__ D1 operator+(double b, const D1& a) { return D1{a.v +
 __device__ __forceinline__ D1 operator-(const D1& a, double b) { return D1{a.v - b, a.d}; }
 __device__ __forceinline__ D1 operator-(double b, const D1& a) { return D1{b - a.v, -a.d}; }
 __device__ __forceinline__ D1 operator-(const D1& a) { return D1{-a.v, -a.d}; }
+__device__ __forceinline__ D1& operator+=(D1& a, const D1& b) { a = a + b; return a; }
+__device__ __forceinline__ D1& operator-=(D1& a, const D1& b) { a = a - b; return a; }
+__device__ __forceinline__ D1& operator*=(D1& a, const D1& b) { a = a * b; return a; }
 __device__ __forceinline__ D1 inv(const D1& a) {
     const double r = frcp(a.v);
     return D1{r, -a.d * r * r};
@@ -287,23 +297,35 @@ __device__ __forceinline__ D1 rsq(const D1& a) {
     const double r = frsqrt(a.v);
     return D1{r, -0.5 * a.d * r * r * r};
 }
+__device__ __forceinline__ D1 frcp(const D1& a) { return inv(a); }
+__device__ __forceinline__ D1 frsqrt(const D1& a) { return rsq(a); }
 __device__ __forceinline__ D1 operator/(const D1& a, const D1& b) { return a * inv(b); }
 __device__ __forceinline__ D1 operator/(double a, const D1& b) { return a * inv(b); }
 __device__ __forceinline__ D1 operator/(const D1& a, double b) { return a * (1.0 / b); }
 __device__ __forceinline__ double val(const D1& x) { return x.v; }
+__device__ __forceinline__ bool operator<(const D1& a, const D1& b) { return a.v < b.v; }
+__device__ __forceinline__ bool operator>(const D1& a, const D1& b) { return a.v > b.v; }
+__device__ __forceinline__ bool operator<=(const D1& a, const D1& b) { return a.v <= b.v; }
+__device__ __forceinline__ bool operator>=(const D1& a, const D1& b) { return a.v >= b.v; }
+__device__ __forceinline__ D1 fabs(const D1& a) { return a.v < 0.0 ? -a : a; }
+__device__ __forceinline__ D1 fmin(const D1& a, const D1& b) { return a.v <= b.v ? a : b; }
+__device__ __forceinline__ D1 fmax(const D1& a, const D1& b) { return a.v >= b.v ? a : b; }
 
-// constant inputs of one recovery
-struct RecIn {
-    double G, D, tau, S[3], Bc[3], Bl[3], Es[3], cfac;   // cfac = a dt alpha sigma
+// inputs of one recovery (T = double, or a dual type when the adjoint
+// differentiates the recovered state with respect to them)
+template <class T> struct RecInT {
+    double G;
+    T D, tau, S[3], Bc[3], Bl[3], Es[3], cfac;   // cfac = a dt alpha sigma; Bl = lowered B / sqrt(gamma)
     double sg, isg, g[6], gi[6];
 };
+using RecIn = RecInT<double>;
 
 // Residual of the recovery map at x = (p, v): r0 = (Gamma-1) rho eps - p,
 // r_i = v'^i - v^i, where E solves the implicit stage equation at v
 // (closed form of eq. 3D_NR), v' is the velocity of Sec. III.B step (iii) at
 // (E, p), and rho, eps follow it.  Returns false if unphysical.
-template <class S>
-__device__ __forceinline__ bool rec_residual(const RecIn& k, const S* x, S* r, double* Eout) {
+template <class S, class K>
+__device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eout) {
     const S p = x[0];
     const S v[3] = {x[1], x[2], x[3]};
     S vl[3];
@@ -343,7 +365,7 @@ __device__ __forceinline__ bool rec_residual(const RecIn& k, const S* x, S* r, d
     r[0] = (k.G - 1.0) * rho * eps - p;
     for (int i = 0; i < 3; ++i) r[1 + i] = w[i] - v[i];
     if (Eout)
-        for (int i = 0; i < 3; ++i) Eout[i] = val(E[i]);
+        for (int i = 0; i < 3; ++i) Eout[i] = E[i];
     return isfinite(val(r[0])) && isfinite(val(r[1])) && isfinite(val(r[2])) && isfinite(val(r[3]));
 }
 
@@ -409,7 +431,7 @@ __device__ __forceinline__ bool rec_jacobian(const RecIn& k, const double* x, do
         D1 xd[4], rd[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) xd[a] = D1{x[a], a == b ? 1.0 : 0.0};
-        if (!rec_residual<D1>(k, xd, rd, nullptr)) return false;
+        if (!rec_residual<D1>(k, xd, rd, (D1*)nullptr)) return false;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             r[a] = rd[a].v;
@@ -428,12 +450,12 @@ __device__ __forceinline__ bool rec_jacobian(const RecIn& k, const double* x, do
 __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, int maxit, int* iters) {
     double r[4];
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
-    if (!rec_residual<double>(k, x, r, nullptr)) {
+    if (!rec_residual<double>(k, x, r, (double*)nullptr)) {
         // outside the physical domain: restart at rest with a larger pressure
         x[1] = x[2] = x[3] = 0.0;
         bool ok = false;
         for (int i = 0; i < 64 && !ok; ++i) {
-            ok = rec_residual<double>(k, x, r, nullptr);
+            ok = rec_residual<double>(k, x, r, (double*)nullptr);
             if (!ok) x[0] *= 2.0;
         }
         if (!ok) { *iters = 0; return ST_UNPHYS; }

@@ -21,7 +21,8 @@ PREC = {"fp64": 0, "mixed": 1}
 
 SYMBOLS = ("rmhd_workspace_bytes", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
-           "rmhd_last_error", "rmhd_timing", "rmhd_timing_read")
+           "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
+           "rmhd_step_adjoint", "rmhd_prim2con_adjoint")
 TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
 
 
@@ -67,6 +68,9 @@ def lib() -> C.CDLL:
             "rmhd_last_error": (C.c_char_p, []),
             "rmhd_timing": (C.c_int, [vp, C.c_int]),
             "rmhd_timing_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+            "rmhd_adjoint_workspace_bytes": (C.c_size_t, [gp]),
+            "rmhd_step_adjoint": (C.c_int, [vp, C.c_double, vp, vp, vp, vp, vp, vp, vp, C.c_size_t]),
+            "rmhd_prim2con_adjoint": (C.c_int, [vp, vp, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -191,6 +195,25 @@ class Grid:
         v = C.c_int64()
         _check(lib().rmhd_failures(self._ctx, C.byref(v)), "rmhd_failures")
         return int(v.value)
+
+    def step_adjoint(self, dt, sigma, U_n, P_n, Ubar_np1, Ubar_n, sigma_bar):
+        """Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1; sigma_bar += (dU^{n+1}/dsigma)^T Ubar_np1.
+        Ubar_n may be Ubar_np1 (in place)."""
+        if getattr(self, "_adj_ws", None) is None:
+            nb = lib().rmhd_adjoint_workspace_bytes(C.byref(self.desc))
+            self._adj_ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+            self._adj_ptr = (self._adj_ws.data_ptr() + 255) // 256 * 256
+            self._adj_bytes = nb
+        _check(lib().rmhd_step_adjoint(self._ctx, float(dt), self._ptr(sigma), self._ptr(U_n, 14),
+                                       self._ptr(P_n, 14), self._ptr(Ubar_np1, 14), self._ptr(Ubar_n, 14),
+                                       self._ptr(sigma_bar), C.c_void_p(self._adj_ptr), self._adj_bytes),
+               "rmhd_step_adjoint")
+
+    def prim2con_adjoint(self, P, Ubar, Pbar=None):
+        Pbar = self.empty() if Pbar is None else Pbar
+        _check(lib().rmhd_prim2con_adjoint(self._ctx, self._ptr(P, 14), self._ptr(Ubar, 14), self._ptr(Pbar, 14)),
+               "rmhd_prim2con_adjoint")
+        return Pbar
 
     def timing(self, enable=True):
         _check(lib().rmhd_timing(self._ctx, 1 if enable else 0), "rmhd_timing")

@@ -216,3 +216,15 @@ def test_mixed_precision_vs_oracle(R, orc, name):
         print(f"[mixed] {name} {NAMES_P[f]}: L1 {l1:.2e} Linf {li:.2e}", flush=True)
         worst = max(worst, l1, li)
     assert worst <= 1e-5
+
+
+@pytest.mark.slow
+def test_sheet_inversion_64x2048_gradient(R):
+    """The 64 x 2048 batch of current sheets, 200 steps, checkpoints every
+    20 steps: the loss gradient in (B^y_0, log sigma) from the adjoint
+    against central differences (h = 1e-6) along 8 random directions."""
+    from test_gpu_adjoint import inversion_fd_check
+    w = W.sheet_batch()
+    worst, L, gB, gs = inversion_fd_check(R, w, ckpt=20, ndir=8)
+    print(f"[rollout] 64x2048 loss {L:.6e} worst rel {worst:.2e}", flush=True)
+    assert worst <= 1e-6
