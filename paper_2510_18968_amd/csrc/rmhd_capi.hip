@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "rmhd.h"
@@ -22,6 +23,7 @@ struct rmhd_ctx {
     double *rhs, *P1, *R1, *U2, *P2, *R2;
     unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits
     bool curved;
+    long persist_blocks = 256;   // persistent flux grid: one 4-wave block per CU, multiple of 8
     // opt-in launch timing: event pairs per kernel class, reused after a read
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[RMHD_TIMING_CLASSES];
@@ -139,25 +141,49 @@ int ghost_fill(rmhd_ctx* c, double* a, int nf) {
     return RMHD_OK;
 }
 
+// x fluxes: in FP64 the persistent kernel (one wave per SIMD walking the
+// segments with the next segment's loads in flight) is faster; in FP32 the
+// one-segment-per-wave kernel is (measured on the 256^3 curved workload)
+template <int D, int RECON, bool CURVED, class R, bool ACC> void flux_t(rmhd_ctx* c, const double* P,
+                                                                     const double* sig) {
+    const Params& p = c->p;
+    constexpr int E1 = (D == 0) ? 1 : 0, E2 = (D == 2) ? 1 : 2;
+    const int nseg = (p.n[D] + TSEG - 1) / TSEG;
+    const long items = (long)nseg * p.n[E1] * p.n[E2];
+    const long need = (nblk(items, 4) + 7) / 8 * 8;   // multiple of 8 for the XCD renumbering
+    if constexpr (std::is_same<R, float>::value) {
+        k_flux_t<D, RECON, CURVED, R, ACC><<<need, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);
+    } else {
+        const long blocks = std::min<long>(need, c->persist_blocks);
+        k_flux_p<D, RECON, CURVED, R, ACC><<<blocks, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);
+    }
+}
+
+template <int D, int RECON, bool CURVED, class R> void flux_w(rmhd_ctx* c, const double* P, const double* sig) {
+    const Params& p = c->p;
+    constexpr int E = (D == 1) ? 2 : 1;
+    const int seglen = 32;
+    const int nxb = (p.n[0] + 63) / 64, nseg = (p.n[D] + seglen - 1) / seglen;
+    const long waves = (long)nxb * p.n[E] * nseg;
+    const long blocks = (waves + 7) / 8 * 8;          // one wave per block; multiple of 8 for the XCD renumbering
+    k_flux_w<D, RECON, CURVED, R><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+}
+
 template <int RECON, bool CURVED, class R> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
     const Params& p = c->p;
-    const long waves = (long)((p.n[0] + XSEG - 1) / XSEG) * p.n[1] * p.n[2];
     {
         Timed t(c, T_FX);
-        k_flux_x<RECON, CURVED, R><<<nblk(waves, 4), 256, 0, c->stream>>>(p, P, sig, c->rhs);
+        flux_t<0, RECON, CURVED, R, false>(c, P, sig);
     }
     LAUNCH_CHECK();
-    const int seglen = 32;
     if (is_active(p, 1)) {
-        dim3 grid(nblk(p.n[0], 64), p.n[2], nblk(p.n[1], seglen));
         Timed t(c, T_FY);
-        k_flux_march<1, RECON, CURVED, R><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
+        flux_w<1, RECON, CURVED, R>(c, P, sig);
         LAUNCH_CHECK();
     }
     if (is_active(p, 2)) {
-        dim3 grid(nblk(p.n[0], 64), p.n[1], nblk(p.n[2], seglen));
         Timed t(c, T_FZ);
-        k_flux_march<2, RECON, CURVED, R><<<grid, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen);
+        flux_w<2, RECON, CURVED, R>(c, P, sig);
         LAUNCH_CHECK();
     }
     return RMHD_OK;
@@ -417,6 +443,12 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     p.kappa = desc->kappa;
     p.tol = desc->c2p_tol;
     c->curved = false;
+    {
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+            c->persist_blocks = ((long)cus + 7) / 8 * 8;
+    }
     k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {

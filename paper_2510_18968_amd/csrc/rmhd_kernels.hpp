@@ -96,154 +96,401 @@ __device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, cons
     for (int a = 0; a < NF; ++a) Fh[a] += cR * F[a] + cU * U[a];
 }
 
-// Reconstruct the 14 fields of the cell at `o` along stride `s` to both faces.
-// Loads are software-pipelined one field ahead and a scheduling barrier per
-// field stops the compiler from hoisting all 70 stencil loads (which would
-// need ~140 extra VGPRs and cut occupancy to one wave per SIMD).  The cell
-// values are kept in FP64 for the cell-centre current.
-template <int RECON, class R>
-__device__ __forceinline__ void recon_cell14(const double* __restrict__ P, long Np, long o, long s, R* fm, R* fp,
-                                             double* Pc) {
-    double cur[5], nxt[5];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) cur[q] = P[o + (q - 2) * s];
-#pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        if (f + 1 < NF) {
-#pragma unroll
-            for (int q = 0; q < 5; ++q) nxt[q] = P[(f + 1) * Np + o + (q - 2) * s];
-        }
-        const R st[5] = {R(cur[0]), R(cur[1]), R(cur[2]), R(cur[3]), R(cur[4])};
-        recon<RECON>(st, fm[f], fp[f]);
-        Pc[f] = cur[2];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (int q = 0; q < 5; ++q) cur[q] = nxt[q];
-    }
+// ----------------------------------------------------- fluxes, lanes along D
+// One wave per segment of TSEG cells along D; lane l holds the cell
+// seg*TSEG - 3 + l, so every lane loads its own 14 primitives and its metric
+// once and takes the stencil neighbours, the right face state and the left
+// face flux from the neighbouring lanes.  Lanes 2..61 reconstruct, faces lie
+// between lanes 2..61, lanes 3..3+TSEG-1 write their divergence.  For D = 1, 2
+// a lane's loads are strided by the row or plane; consecutive waves take
+// consecutive x so that one 128-byte line serves 16 waves, and workgroups are
+// renumbered so that those waves run on one XCD (one L2).
+constexpr int TSEG = 58;
+
+// workgroups go round-robin to the 8 XCDs: renumber so that consecutive
+// logical workgroups share an XCD (gridDim.x is a multiple of 8)
+__device__ __forceinline__ long xcd_block() {
+    const unsigned nb = gridDim.x, b = blockIdx.x;
+    return (long)(b & 7u) * (long)(nb >> 3) + (long)(b >> 3);
 }
 
-// ------------------------------------------------------------------ x fluxes
-constexpr int XSEG = 62;
+// v, with a data dependency on dep: keeps the compiler from hoisting the lane
+// shuffles of v above the work that produced dep (which would keep every
+// field's stencil live at once)
+template <class R, class T> __device__ __forceinline__ R after(R v, T dep) {
+    asm volatile("" : "+v"(v) : "v"(dep));
+    return v;
+}
 
-// R: arithmetic of reconstruction, HLLE and divergence (double, or float in
-// the mixed-precision form); state and rhs stay double.
-template <int RECON, bool CURVED, class R>
-__global__ __launch_bounds__(256) void k_flux_x(const Params p, const double* __restrict__ P,
-                                                const double* __restrict__ sig, double* __restrict__ rhs) {
-    const int lane = threadIdx.x & 63;
-    const long wid = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nseg = (p.n[0] + XSEG - 1) / XSEG;
-    const long nrows = (long)p.n[1] * p.n[2];
-    if (wid >= nrows * nseg) return;
-    const int seg = (int)(wid % nseg);
-    const long row = wid / nseg;
-    const int j = (int)(row % p.n[1]) + p.g[1];
-    const int k = (int)(row / p.n[1]) + p.g[2];
-    const int ilast = p.g[0] + p.n[0];                 // right ghost next to the last cell
-    const int i = p.g[0] - 1 + seg * XSEG + lane;     // this lane's cell (padded index)
-    const int ic = i <= ilast ? i : ilast;
-    const long o = ((long)k * p.np[1] + j) * p.np[0] + ic;
-    const long Np = p.Np;
+template <class R> __device__ __forceinline__ R face4(R a) {
+    // value at the face between this lane's cell and the next one, 4th order
+    const R am = __shfl_up(a, 1), ap = __shfl_down(a, 1), app = __shfl_down(a, 2);
+    return (-am + 9.0 * a + 9.0 * ap - app) * 0.0625;
+}
 
-    R fm[NF], fp[NF];
-    double Pc[NF];
-    recon_cell14<RECON>(P, Np, o, 1, fm, fp, Pc);
-    // cell-centre current, x component (charge flux at faces = mean of the two
-    // cells); FP64 in every form: sigma multiplies a near-cancelling bracket
-    Geo<double> mc;
+// inputs of one lane for one segment: its cell's primitives, metric and sigma
+struct FluxIn {
+    double P[NF], g[6], a, b[3], s;
+};
+
+// wave item -> segment and transverse position; o = this lane's padded offset
+template <int D> struct FluxItem {
+    int seg, c, cp;
+    long o;
+};
+
+template <int D>
+__device__ __forceinline__ FluxItem<D> flux_item(const Params& p, long wid, int nseg, int lane) {
+    constexpr int E1 = (D == 0) ? 1 : 0, E2 = (D == 2) ? 1 : 2;
+    const long n1 = p.n[E1];
+    FluxItem<D> it;
+    long a1, a2;
+    if (D == 0) {
+        it.seg = (int)(wid % nseg);
+        const long r = wid / nseg;
+        a1 = r % n1;
+        a2 = r / n1;
+    } else {
+        a1 = wid % n1;
+        const long r = wid / n1;
+        it.seg = (int)(r % nseg);
+        a2 = r / nseg;
+    }
+    const int nD = p.n[D], gD = p.g[D];
+    it.c = it.seg * TSEG - 3 + lane;                                // interior index of the lane's cell
+    it.cp = min(max(it.c + gD, 0), nD + 2 * gD - 1);                // padded; clamped on unused edge lanes
+    it.o = (a1 + p.g[E1]) * p.st[E1] + (a2 + p.g[E2]) * p.st[E2] + (long)it.cp * p.st[D];
+    return it;
+}
+
+template <int D, bool CURVED>
+__device__ __forceinline__ void flux_load(const Params& p, const double* __restrict__ P,
+                                          const double* __restrict__ sig, const FluxItem<D>& it, FluxIn& in) {
+    const long Np = p.Np, o = it.o;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) in.P[f] = P[f * Np + o];
     if (CURVED) {
-        mc.alp = 1.0;
-        mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
-        for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
+#pragma unroll
+        for (int a = 0; a < 6; ++a) in.g[a] = p.gam[a * Np + o];
+        in.a = p.alp[o];
+        if (p.bet) {
+#pragma unroll
+            for (int a = 0; a < 3; ++a) in.b[a] = p.bet[a * Np + o];
+        }
+    }
+    in.s = sig[o + (long)(bc_map(p, D, it.cp) - it.cp) * p.st[D]];
+}
+
+// minus the D-flux divergence of one segment into rhs (= or +=)
+template <int D, int RECON, bool CURVED, class R, bool ACC>
+__device__ __forceinline__ void flux_compute(const Params& p, const double* __restrict__ P,
+                                             double* __restrict__ rhs, const FluxItem<D>& it, const FluxIn& in,
+                                             int lane) {
+    const long s = p.st[D], Np = p.Np, o = it.o;
+    const int nD = p.n[D], gD = p.g[D];
+    const bool cell = lane >= 3 && lane < 3 + TSEG && it.c < nD;
+    double acc[NF];
+    if (ACC) {
+        // the read half of the read-modify-write, issued before the arithmetic
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f] = cell ? rhs[f * Np + o] : 0.0;
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) acc[f] = 0.0;
+    }
+    Geo<double> mc;   // the lane's cell
+    if (CURVED) {
+        mc.alp = in.a;
+        for (int a = 0; a < 3; ++a) mc.bet[a] = p.bet ? in.b[a] : 0.0;
+        for (int a = 0; a < 6; ++a) mc.g[a] = in.g[a];
         geo_finish(mc);
     } else {
         geo_flat(mc);
     }
-    const long os = o - ic + bc_map(p, 0, ic);
-    double J[3];
-    current(mc, Pc, sig[os], J);
-    const double JR = __shfl_down(J[0], 1);
+    __builtin_amdgcn_sched_barrier(0);
+    // cell-centre current (FP64 in every form), face value = mean of the two cells
+    double JD;
+    {
+        double J[3];
+        current(mc, in.P, in.s, J);
+        JD = J[D];
+    }
+    const R Jf = R(0.5 * (JD + __shfl_down(JD, 1)));
+    __builtin_amdgcn_sched_barrier(0);
+    R fm[NF], fp[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        // two fields in flight: the shuffles of f wait for field f - 2
+        const R v = f >= 2 ? after(R(in.P[f]), fp[f - 2]) : R(in.P[f]);
+        const R st[5] = {__shfl_up(v, 2), __shfl_up(v, 1), v, __shfl_down(v, 1), __shfl_down(v, 2)};
+        recon<RECON>(st, fm[f], fp[f]);
+    }
+    // face between this lane's cell and the next
+    Geo<R> m;
+    if (CURVED) {
+        m.alp = R(face4(in.a));
+        for (int a = 0; a < 3; ++a) m.bet[a] = p.bet ? R(face4(in.b[a])) : R(0);
+        m.g[0] = R(face4(in.g[0]));
+        for (int a = 1; a < 6; ++a) m.g[a] = R(face4(after(in.g[a], m.g[a - 1])));
+        geo_finish(m);
+    } else {
+        geo_flat(m);
+    }
     R PR[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) PR[f] = __shfl_down(fm[f], 1);
-
-    // face i + 1/2
-    Geo<R> m;
-    if (CURVED) face_geo(p, o, 1, m); else geo_flat(m);
-    if (bad_state(m, fp))
-        for (int f = 0; f < NF; ++f) fp[f] = R(P[f * Np + o]);
-    if (bad_state(m, PR))
-        for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + o + 1]);
+    __builtin_amdgcn_sched_barrier(0);
+    // first-order fallback; only faces whose right cell lies inside the padded
+    // range (the clamped edge lanes carry no face that is used)
+    const bool face = it.cp + 1 < nD + 2 * gD;
+    if (face && bad_state(m, fp))
+        for (int f = 0; f < NF; ++f) fp[f] = R(in.P[f]);
+    if (face && bad_state(m, PR))
+        for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + o + s]);
     R Fh[NF];
-    face_flux<0>(p, m, fp, PR, R(0.5 * (J[0] + JR)), Fh);
+    face_flux<D>(p, m, fp, PR, Jf, Fh);
 
-    const bool cell = lane >= 1 && lane <= XSEG && i >= p.g[0] && i < ilast;
-    const R ih = R(p.idx[0]);
+    if (CURVED) {
+        // source terms with the metric derivatives along D, 4th-order centred
+        // differences from the neighbouring lanes
+        const double cd = p.idx[D] / 12.0;
+        auto dD = [&](double f) {
+            const double m2 = __shfl_up(f, 2), m1 = __shfl_up(f, 1), p1 = __shfl_down(f, 1), p2 = __shfl_down(f, 2);
+            return (m2 - 8.0 * m1 + 8.0 * p1 - p2) * cd;
+        };
+        double dg[6], db[3] = {0.0, 0.0, 0.0};
+        const double da = dD(in.a);
+        if (p.bet)
+            for (int a = 0; a < 3; ++a) db[a] = dD(in.b[a]);
+        for (int a = 0; a < 6; ++a) dg[a] = dD(in.g[a]);
+        double Uc[NF];
+        prim2con(mc, p.G, in.P, Uc);
+        sources_dir<D>(p, mc, da, db, dg, in.P, Uc, acc);
+    }
+    const R ih = R(p.idx[D]);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const R Fl = __shfl_up(Fh[f], 1);
-        if (cell) rhs[f * Np + o] = double(-(Fh[f] - Fl) * ih);
+        if (cell) rhs[f * Np + o] = acc[f] + double(-(Fh[f] - Fl) * ih);
     }
 }
 
-// -------------------------------------------------------------- y / z fluxes
+// one segment per wave
+template <int D, int RECON, bool CURVED, class R, bool ACC>
+__global__ __launch_bounds__(256) void k_flux_t(const Params p, const double* __restrict__ P,
+                                                const double* __restrict__ sig, double* __restrict__ rhs,
+                                                int nseg, long nitems) {
+    const int lane = threadIdx.x & 63;
+    const long wid = xcd_block() * 4 + (threadIdx.x >> 6);
+    if (wid >= nitems) return;                       // uniform per wave
+    const FluxItem<D> it = flux_item<D>(p, wid, nseg, lane);
+    FluxIn in;
+    flux_load<D, CURVED>(p, P, sig, it, in);
+    flux_compute<D, RECON, CURVED, R, ACC>(p, P, rhs, it, in, lane);
+}
+
+// persistent: one wave per SIMD walks the segments wid, wid + W, ..., loading
+// the next segment's inputs while it computes the current one
+template <int D, int RECON, bool CURVED, class R, bool ACC>
+__global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __restrict__ P,
+                                                const double* __restrict__ sig, double* __restrict__ rhs,
+                                                int nseg, long nitems) {
+    const int lane = threadIdx.x & 63;
+    const long W = (long)gridDim.x * 4;
+    long wid = xcd_block() * 4 + (threadIdx.x >> 6);
+    if (wid >= nitems) return;                       // uniform per wave
+    FluxItem<D> it = flux_item<D>(p, wid, nseg, lane);
+    FluxIn in;
+    flux_load<D, CURVED>(p, P, sig, it, in);
+    for (;;) {
+        const long nxt = wid + W;
+        FluxItem<D> it2 = it;
+        FluxIn in2;
+        if (nxt < nitems) {
+            it2 = flux_item<D>(p, nxt, nseg, lane);
+            flux_load<D, CURVED>(p, P, sig, it2, in2);
+        }
+        flux_compute<D, RECON, CURVED, R, ACC>(p, P, rhs, it, in, lane);
+        if (nxt >= nitems) break;
+        wid = nxt;
+        it = it2;
+        in = in2;
+    }
+}
+
+// ------------------------------------------- y / z fluxes: rolling window
+// Lanes along x (coalesced 512-byte rows), one wave marches a segment of
+// cells along D.  Every row of P and sigma is loaded once, into a per-lane
+// ring of the last five rows in LDS (38.4 KB per wave); the metric rows of
+// the window (c-3 .. c+2) stay in registers.  Step c: reconstruct c from rows
+// c-2..c+2 and take its current; face c-1/2 from the carried right state of
+// c-1 and the left state of c; rhs of c-1 = rhs + its sources (derivatives
+// from rows c-3..c+1) - the flux difference.  Lanes never exchange data.
+constexpr int WRING = 5, WNF = NF + 1;   // ring slots, fields per slot (P + sigma)
+
 template <int D, int RECON, bool CURVED, class R>
-__global__ __launch_bounds__(64) void k_flux_march(const Params p, const double* __restrict__ P,
-                                                   const double* __restrict__ sig, double* __restrict__ rhs,
-                                                   int seglen) {
-    const int i = blockIdx.x * 64 + threadIdx.x;
-    if (i >= p.n[0]) return;
-    constexpr int E = (D == 1) ? 2 : 1;               // the other transverse dimension
-    const int e = blockIdx.y + p.g[E];
-    const int c0 = blockIdx.z * seglen;               // first cell (interior index) of the segment
-    const int c1 = min(c0 + seglen, p.n[D]);
-    const long s = p.st[D];
-    const long Np = p.Np;
-    const long base = (long)(i + p.g[0]) + (long)e * p.st[E];
+__global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __restrict__ P,
+                                               const double* __restrict__ sig, double* __restrict__ rhs,
+                                               int seglen, int nxb, int nseg) {
+    constexpr int E = (D == 1) ? 2 : 1;                 // the other transverse dimension
+    __shared__ double ring[WRING * WNF * 64];
+    const int lane = threadIdx.x;
+    const long wid = xcd_block();
+    if (wid >= (long)nxb * p.n[E] * nseg) return;      // uniform per wave
+    const int xb = (int)(wid % nxb);
+    const long r = wid / nxb;
+    const int e = (int)(r % p.n[E]);
+    const int seg = (int)(r / p.n[E]);
+    const int i = xb * 64 + lane;
+    if (i >= p.n[0]) return;                            // lanes are independent
+    const int nD = p.n[D], gD = p.g[D];
+    const int c0 = seg * seglen, c1 = min(c0 + seglen, nD);
+    const long s = p.st[D], Np = p.Np;
+    const long base = (long)(i + p.g[0]) + (long)(e + p.g[E]) * p.st[E];
     const R ih = R(p.idx[D]);
+    const double cd = p.idx[D] / 12.0;
+    double* rw = ring + lane;
+    auto ringP = [&](int c, int f) -> double& { return rw[(((c + gD) % WRING) * WNF + f) * 64]; };
+
+    // metric window, index k <-> row c - 3 + k
+    double wa[6], wb[6][3], wg[6][6];
+    auto load_metric = [&](int c, double& ar, double* br, double* gr) {
+        const long o = base + (long)(c + gD) * s;
+        ar = p.alp[o];
+        for (int a = 0; a < 3; ++a) br[a] = p.bet ? p.bet[a * Np + o] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) gr[a] = p.gam[a * Np + o];
+    };
+    auto load_ring = [&](int c) {
+        const long o = base + (long)(c + gD) * s;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ringP(c, f) = P[f * Np + o];
+        ringP(c, NF) = sig[o + (long)(bc_map(p, D, c + gD) - (c + gD)) * s];
+    };
+    // window of the first step (c = c0 - 1): P rows c0-3 .. c0+1, metric rows
+    // c0-4 .. c0+1 (row c0-4 is outside the padding when c0 = 0 and unused)
+    for (int c = c0 - 3; c <= c0 + 1; ++c) load_ring(c);
+    if (CURVED) {
+        for (int k = 0; k < 6; ++k) {
+            const int c = c0 - 4 + k;
+            if (c >= -gD) {
+                load_metric(c, wa[k], wb[k], wg[k]);
+            } else {
+                wa[k] = 0.0;
+                for (int a = 0; a < 3; ++a) wb[k][a] = 0.0;
+                for (int a = 0; a < 6; ++a) wg[k][a] = 0.0;
+            }
+        }
+    }
 
     R PLc[NF], Fprev[NF];
     double Jprev = 0.0;
 #pragma unroll 1
     for (int c = c0 - 1; c <= c1; ++c) {
-        const int cp = c + p.g[D];
-        const long o = base + (long)cp * s;
-        R fm[NF], fp[NF];
-        double Pc[NF];
-        recon_cell14<RECON>(P, Np, o, s, fm, fp, Pc);
-        Geo<double> mc;
-        if (CURVED) {
-            mc.alp = 1.0;
-            mc.bet[0] = mc.bet[1] = mc.bet[2] = 0.0;
-            for (int a = 0; a < 6; ++a) mc.g[a] = p.gam[a * Np + o];
-            geo_finish(mc);
-        } else {
-            geo_flat(mc);
-        }
-        const long os = o + (long)(bc_map(p, D, cp) - cp) * s;
-        double J[3];
-        current(mc, Pc, sig[os], J);
-        if (c >= c0) {
-            // face between c - 1 and c
-            Geo<R> m;
-            if (CURVED) face_geo(p, o - s, s, m); else geo_flat(m);
-            if (bad_state(m, PLc))
-                for (int f = 0; f < NF; ++f) PLc[f] = R(P[f * Np + o - s]);
-            if (bad_state(m, fm))
-                for (int f = 0; f < NF; ++f) fm[f] = R(P[f * Np + o]);
-            R Fh[NF];
-            face_flux<D>(p, m, PLc, fm, R(0.5 * (Jprev + J[D])), Fh);
-            if (c > c0) {
-                const long oc = o - s;
+        const bool fin = c - 1 >= c0;                   // rhs of c - 1 is finished this step
+        const long om = base + (long)(c - 1 + gD) * s;
+        double acc[NF];
+        if (fin) {
 #pragma unroll
-                for (int f = 0; f < NF; ++f) rhs[f * Np + oc] -= double((Fh[f] - Fprev[f]) * ih);
+            for (int f = 0; f < NF; ++f) acc[f] = rhs[f * Np + om];
+            if (CURVED) {
+                // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
+                Geo<double> ms;
+                ms.alp = wa[2];
+                for (int a = 0; a < 3; ++a) ms.bet[a] = wb[2][a];
+                for (int a = 0; a < 6; ++a) ms.g[a] = wg[2][a];
+                geo_finish(ms);
+                auto d4 = [&](double a0, double a1, double a3, double a4) {
+                    return (a0 - 8.0 * a1 + 8.0 * a3 - a4) * cd;
+                };
+                const double da = d4(wa[0], wa[1], wa[3], wa[4]);
+                double db[3], dg[6];
+                for (int a = 0; a < 3; ++a) db[a] = d4(wb[0][a], wb[1][a], wb[3][a], wb[4][a]);
+                for (int a = 0; a < 6; ++a) dg[a] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
+                double Pm[NF], Um[NF];
+#pragma unroll
+                for (int f = 0; f < NF; ++f) Pm[f] = ringP(c - 1, f);
+                prim2con(ms, p.G, Pm, Um);
+                sources_dir<D>(p, ms, da, db, dg, Pm, Um, acc);
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // current of c (metric row c: window 3)
+        double Jc;
+        {
+            Geo<double> mc;
+            if (CURVED) {
+                mc.alp = wa[3];
+                for (int a = 0; a < 3; ++a) mc.bet[a] = wb[3][a];
+                for (int a = 0; a < 6; ++a) mc.g[a] = wg[3][a];
+                geo_finish(mc);
+            } else {
+                geo_flat(mc);
+            }
+            double Pc[NF], J[3];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) Pc[f] = ringP(c, f);
+            current(mc, Pc, ringP(c, NF), J);
+            Jc = J[D];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        // reconstruction of c
+        R fm[NF], fp[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            // two fields in flight: the ring reads of f wait for field f - 2
+            const int sl = f >= 2 ? after(0, fp[f - 2]) : 0;
+            const R st[5] = {R(ringP(c - 2, f + sl)), R(ringP(c - 1, f + sl)), R(ringP(c, f + sl)),
+                             R(ringP(c + 1, f + sl)), R(ringP(c + 2, f + sl))};
+            recon<RECON>(st, fm[f], fp[f]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        if (c >= c0) {
+            // face c - 1/2: metric at the face from rows c-2 .. c+1 (window 1..4)
+            Geo<R> m;
+            if (CURVED) {
+                auto f4 = [](double a0, double a1, double a2, double a3) {
+                    return (-a0 + 9.0 * a1 + 9.0 * a2 - a3) * 0.0625;
+                };
+                m.alp = R(f4(wa[1], wa[2], wa[3], wa[4]));
+                for (int a = 0; a < 3; ++a) m.bet[a] = R(f4(wb[1][a], wb[2][a], wb[3][a], wb[4][a]));
+                for (int a = 0; a < 6; ++a) m.g[a] = R(f4(wg[1][a], wg[2][a], wg[3][a], wg[4][a]));
+                geo_finish(m);
+            } else {
+                geo_flat(m);
+            }
+            if (bad_state(m, PLc))
+                for (int f = 0; f < NF; ++f) PLc[f] = R(ringP(c - 1, f));
+            R PR[NF];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) PR[f] = fm[f];
+            if (bad_state(m, PR))
+                for (int f = 0; f < NF; ++f) PR[f] = R(ringP(c, f));
+            R Fh[NF];
+            face_flux<D>(p, m, PLc, PR, R(0.5 * (Jprev + Jc)), Fh);
+            if (fin) {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) rhs[f * Np + om] = acc[f] + double(-(Fh[f] - Fprev[f]) * ih);
             }
 #pragma unroll
             for (int f = 0; f < NF; ++f) Fprev[f] = Fh[f];
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) PLc[f] = fp[f];
-        Jprev = J[D];
+        Jprev = Jc;
+        // advance the window by one row
+        if (c < c1) {
+            load_ring(c + 3);
+            if (CURVED) {
+#pragma unroll
+                for (int k = 0; k < 5; ++k) {
+                    wa[k] = wa[k + 1];
+                    for (int a = 0; a < 3; ++a) wb[k][a] = wb[k + 1][a];
+                    for (int a = 0; a < 6; ++a) wg[k][a] = wg[k + 1][a];
+                }
+                load_metric(c + 3, wa[5], wb[5], wg[5]);
+            }
+        }
     }
 }
 
@@ -400,38 +647,19 @@ __device__ __forceinline__ void metric_derivs(const Params& p, long o, MetricDer
         for (int a = 0; a < 6; ++a) md.K[a] = p.K[a * p.Np + o];
 }
 
-// eq. GRRMHD_flux_form sources at a cell centre, E rows without R_E.
-// R: double, or the dual type of the adjoint's tangent passes (the metric
-// is fixed input and enters as double)
-template <bool CURVED, class R>
-__device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m, const MetricDerivs& md,
-                                          const R* Pc, const R* Uc, R* S) {
+// eq. GRRMHD_flux_form sources at a cell centre, E rows without R_E, split
+// into the terms without metric derivatives (sources_local) and, for each
+// direction d, the terms linear in d_d alpha, d_d beta^i, d_d gamma_ij
+// (sources_dir<d>).  Every derivative term carries one derivative, so the sum
+// over d of sources_dir plus sources_local is the whole source.  The flux
+// kernel of direction d adds sources_dir<d> (its lanes hold the metric along
+// d, so the derivative costs four lane shuffles per field); the stage kernels
+// add sources_local.  R: double, or the dual type of the adjoint's passes.
+
+// densitised stress S^{jk} (both indices up) of a cell state
+template <class R>
+__device__ __forceinline__ void stress_up(const Params& p, const Geo<double>& m, const R* Pc, R* Su) {
     const R* v = Pc + I_V;
-    const double kap = p.kappa;
-    if (!CURVED) {
-        for (int f = 0; f < NF; ++f) S[f] = R(0.0);
-        for (int i = 0; i < 3; ++i) S[I_E + i] = -(Uc[I_Q] * v[i]);
-        S[I_PHI] = -(Uc[I_PHI] * kap);
-        S[I_PSI] = Uc[I_Q] - Uc[I_PSI] * kap;
-        return;
-    }
-    const double a = m.alp;
-    // Gamma^i = gamma^il (gamma^jk d_j gamma_lk - 1/2 gamma^jk d_l gamma_jk)
-    double A[3], Gm[3], gda[3];
-    for (int l = 0; l < 3; ++l) {
-        double s1 = 0.0, s2 = 0.0;
-        for (int j = 0; j < 3; ++j)
-            for (int kk = 0; kk < 3; ++kk) {
-                s1 += m.gi[sidx(j, kk)] * md.dg[j][sidx(l, kk)];
-                s2 += m.gi[sidx(j, kk)] * md.dg[l][sidx(j, kk)];
-            }
-        A[l] = s1 - 0.5 * s2;
-    }
-    for (int i = 0; i < 3; ++i) {
-        Gm[i] = m.gi[sidx(i, 0)] * A[0] + m.gi[sidx(i, 1)] * A[1] + m.gi[sidx(i, 2)] * A[2];
-        gda[i] = m.gi[sidx(i, 0)] * md.da[0] + m.gi[sidx(i, 1)] * md.da[1] + m.gi[sidx(i, 2)] * md.da[2];
-    }
-    // densitised stress with both indices up
     const R* B = Pc + I_B;
     const R* E = Pc + I_E;
     R vl[3], Bl[3], El[3];
@@ -441,52 +669,88 @@ __device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m,
     const R W = frsqrt(R(1.0) - dot3(vl, v));
     const R hW2 = (Pc[I_RHO] + Pc[I_P] * (p.G / (p.G - 1.0))) * (W * W);
     const R pt = Pc[I_P] + (dot3(El, E) + dot3(Bl, B)) * 0.5;
-    R Su[6];
     for (int j = 0; j < 3; ++j)
         for (int kk = j; kk < 3; ++kk)
             Su[sidx(j, kk)] = (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk] + pt * m.gi[sidx(j, kk)]) * m.sg;
-    const R* Sl = Uc + I_S;
-    R Sup[3];
-    for (int i = 0; i < 3; ++i) Sup[i] = Sl[0] * m.gi[sidx(i, 0)] + Sl[1] * m.gi[sidx(i, 1)] + Sl[2] * m.gi[sidx(i, 2)];
+}
+
+// S = the terms without metric derivatives (K: extrinsic curvature, used if hasK)
+template <bool CURVED, class R>
+__device__ __forceinline__ void sources_local(const Params& p, const Geo<double>& m, const double (&K)[6], bool hasK,
+                                              const R* Pc, const R* Uc, R* S) {
+    const R* v = Pc + I_V;
+    const double kap = p.kappa;
+    for (int f = 0; f < NF; ++f) S[f] = R(0.0);
+    if (!CURVED) {
+        for (int i = 0; i < 3; ++i) S[I_E + i] = -(Uc[I_Q] * v[i]);
+        S[I_PHI] = -(Uc[I_PHI] * kap);
+        S[I_PSI] = Uc[I_Q] - Uc[I_PSI] * kap;
+        return;
+    }
+    const double a = m.alp;
     double Ktr = 0.0;
     R SK = R(0.0);
-    if (p.K) {
+    if (hasK) {
+        R Su[6];
+        stress_up(p, m, Pc, Su);
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
-                const double kij = md.K[sidx(i, j)];
+                const double kij = K[sidx(i, j)];
                 Ktr += m.gi[sidx(i, j)] * kij;
                 SK += Su[sidx(i, j)] * kij;
             }
     }
-    S[I_D] = R(0.0);
-    for (int i = 0; i < 3; ++i) {
-        R t = R(0.0);
-        for (int j = 0; j < 3; ++j)
-            for (int kk = 0; kk < 3; ++kk) t += Su[sidx(j, kk)] * md.dg[i][sidx(j, kk)];
-        S[I_S + i] = t * (0.5 * a) + (Sl[0] * md.db[i][0] + Sl[1] * md.db[i][1] + Sl[2] * md.db[i][2]) -
-                     (Uc[I_TAU] + Uc[I_D]) * md.da[i];
-    }
-    S[I_TAU] = SK * a - (Sup[0] * md.da[0] + Sup[1] * md.da[1] + Sup[2] * md.da[2]);
-    for (int i = 0; i < 3; ++i) {
-        const R bb = Uc[I_B] * md.db[0][i] + Uc[I_B + 1] * md.db[1][i] + Uc[I_B + 2] * md.db[2][i];
-        const R eb = Uc[I_E] * md.db[0][i] + Uc[I_E + 1] * md.db[1][i] + Uc[I_E + 2] * md.db[2][i];
-        const double gg = gda[i] - a * Gm[i];
-        S[I_B + i] = Uc[I_PHI] * gg - bb;
-        S[I_E + i] = Uc[I_PSI] * gg - eb - Uc[I_Q] * v[i] * a;
-    }
-    S[I_PHI] = -(Uc[I_PHI] * (a * Ktr)) + (Uc[I_B] * md.da[0] + Uc[I_B + 1] * md.da[1] + Uc[I_B + 2] * md.da[2]) -
-               Uc[I_PHI] * (a * kap);
-    S[I_PSI] = -(Uc[I_PSI] * (a * Ktr)) + (Uc[I_E] * md.da[0] + Uc[I_E + 1] * md.da[1] + Uc[I_E + 2] * md.da[2]) +
-               Uc[I_Q] * a - Uc[I_PSI] * (a * kap);
-    S[I_Q] = R(0.0);
+    S[I_TAU] = SK * a;
+    for (int i = 0; i < 3; ++i) S[I_E + i] = -(Uc[I_Q] * v[i] * a);
+    S[I_PHI] = -(Uc[I_PHI] * (a * Ktr)) - Uc[I_PHI] * (a * kap);
+    S[I_PSI] = -(Uc[I_PSI] * (a * Ktr)) + Uc[I_Q] * a - Uc[I_PSI] * (a * kap);
 }
 
-template <bool CURVED>
-__device__ __forceinline__ void sources(const Params& p, long o, const Geo<double>& m, const double* Pc,
-                                        const double* Uc, double* S) {
-    MetricDerivs md;
-    metric_derivs<CURVED>(p, o, md);
-    sources_t<CURVED, double>(p, m, md, Pc, Uc, S);
+// S += the terms with the derivatives along d: da = d_d alpha, db[i] =
+// d_d beta^i, dg[jk] = d_d gamma_jk.  Gamma^i = gamma^il A_l with
+// A_l = gamma^jk d_j gamma_lk - 1/2 gamma^jk d_l gamma_jk.
+template <int d, class R>
+__device__ __forceinline__ void sources_dir(const Params& p, const Geo<double>& m, double da, const double* db,
+                                            const double* dg, const R* Pc, const R* Uc, R* S) {
+    const double a = m.alp;
+    R Su[6];
+    stress_up(p, m, Pc, Su);
+    // A_l restricted to the d-derivatives: gamma^dk dg[lk] - 1/2 delta_ld gamma^jk dg[jk]
+    double A[3];
+    double tr = 0.0;
+    for (int j = 0; j < 3; ++j)
+        for (int kk = 0; kk < 3; ++kk) tr += m.gi[sidx(j, kk)] * dg[sidx(j, kk)];
+    for (int l = 0; l < 3; ++l) {
+        double s1 = 0.0;
+        for (int kk = 0; kk < 3; ++kk) s1 += m.gi[sidx(d, kk)] * dg[sidx(l, kk)];
+        A[l] = s1 - (l == d ? 0.5 * tr : 0.0);
+    }
+    const R* Sl = Uc + I_S;
+    R t = R(0.0);
+    for (int j = 0; j < 3; ++j)
+        for (int kk = 0; kk < 3; ++kk) t += Su[sidx(j, kk)] * dg[sidx(j, kk)];
+    S[I_S + d] += t * (0.5 * a) + (Sl[0] * db[0] + Sl[1] * db[1] + Sl[2] * db[2]) - (Uc[I_TAU] + Uc[I_D]) * da;
+    const R Supd = Sl[0] * m.gi[sidx(d, 0)] + Sl[1] * m.gi[sidx(d, 1)] + Sl[2] * m.gi[sidx(d, 2)];
+    S[I_TAU] += -(Supd * da);
+    for (int i = 0; i < 3; ++i) {
+        const double Gm = m.gi[sidx(i, 0)] * A[0] + m.gi[sidx(i, 1)] * A[1] + m.gi[sidx(i, 2)] * A[2];
+        const double gg = m.gi[sidx(i, d)] * da - a * Gm;
+        S[I_B + i] += Uc[I_PHI] * gg - Uc[I_B + d] * db[i];
+        S[I_E + i] += Uc[I_PSI] * gg - Uc[I_E + d] * db[i];
+    }
+    S[I_PHI] += Uc[I_B + d] * da;
+    S[I_PSI] += Uc[I_E + d] * da;
+}
+
+// whole source at a cell centre from its metric derivatives
+template <bool CURVED, class R>
+__device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m, const MetricDerivs& md,
+                                          const R* Pc, const R* Uc, R* S) {
+    sources_local<CURVED>(p, m, md.K, p.K != nullptr, Pc, Uc, S);
+    if (!CURVED) return;
+    sources_dir<0>(p, m, md.da[0], md.db[0], md.dg[0], Pc, Uc, S);
+    sources_dir<1>(p, m, md.da[1], md.db[1], md.dg[1], Pc, Uc, S);
+    sources_dir<2>(p, m, md.da[2], md.db[2], md.dg[2], Pc, Uc, S);
 }
 
 // --------------------------------------------------------------- stages
@@ -562,7 +826,11 @@ __global__ __launch_bounds__(256) void k_update(const Params p, double dt, const
             double Pc[NF], Uc[NF], S[NF];
             for (int f = 0; f < NF; ++f) Pc[f] = Ps[f * Np + o];
             prim2con(m, p.G, Pc, Uc);
-            sources<CURVED>(p, o, m, Pc, Uc, S);
+            // derivative terms were added by the flux kernels
+            double K[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (CURVED && p.K)
+                for (int a = 0; a < 6; ++a) K[a] = p.K[a * Np + o];
+            sources_local<CURVED>(p, m, K, CURVED && p.K, Pc, Uc, S);
             x[0] = Pc[I_P];
             x[1] = Pc[I_V];
             x[2] = Pc[I_V + 1];
