@@ -208,31 +208,33 @@ int flux_div(rmhd_ctx* c, const double* P, const double* sig) {
     return flux_div_r<double>(c, P, sig);
 }
 
-int stage1(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Pg, double* P1, double* R1,
-           double* U1, int32_t* st) {
-    const long n = ncells(c->p);
-    Timed t(c, T_STAGE1);
+// persistent stage kernels: one 4-wave block per CU (one wave per SIMD)
+template <int STAGE>
+int launch_stage(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Us, const double* Ps,
+                 const double* R1, const double* R2, double* Uo, double* Po, double* Ro, int32_t* st) {
+    const long nchunk = (ncells(c->p) + 63) / 64;
+    const long blocks = std::max<long>(1, std::min<long>(c->persist_blocks, (nchunk + 3) / 4));
     if (c->curved)
-        k_stage1<true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Pg, P1, R1, U1, st, c->counters);
+        k_stage<STAGE, true><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po, Ro,
+                                                             st, c->counters);
     else
-        k_stage1<false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Pg, P1, R1, U1, st, c->counters);
+        k_stage<STAGE, false><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po, Ro,
+                                                              st, c->counters);
     LAUNCH_CHECK();
     return RMHD_OK;
+}
+
+int stage1(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Pg, double* P1, double* R1,
+           double* U1, int32_t* st) {
+    Timed t(c, T_STAGE1);
+    return launch_stage<1>(c, dt, sig, Un, nullptr, Pg, nullptr, nullptr, U1, P1, R1, st);
 }
 
 template <int STAGE>
 int update(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Us, const double* Ps,
            const double* R1, const double* R2, double* Uo, double* Po, double* Ro, int32_t* st) {
-    const long n = ncells(c->p);
     Timed t(c, STAGE == 2 ? T_UPD2 : T_UPD3);
-    if (c->curved)
-        k_update<STAGE, true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                   Ro, st, c->counters);
-    else
-        k_update<STAGE, false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo,
-                                                                    Po, Ro, st, c->counters);
-    LAUNCH_CHECK();
-    return RMHD_OK;
+    return launch_stage<STAGE>(c, dt, sig, Un, Us, Ps, R1, R2, Uo, Po, Ro, st);
 }
 
 int stage2(rmhd_ctx* c, double dt, const double* sig, const double* Un, double* P1, const double* R1, double* U2,

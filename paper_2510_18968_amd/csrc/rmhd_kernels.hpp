@@ -573,10 +573,10 @@ __device__ __forceinline__ void write_prims(const Params& p, long o, const Geo<d
     for (int f = I_PHI; f < NF; ++f) P[f * p.Np + o] = U[f] * m.isg;
 }
 
-// primitives at a recovered root from RecIn (D, Bcal) and the cleaning and
-// charge rows of the conserved array U (global)
+// primitives at a recovered root from RecIn (D, Bcal) and the conserved
+// cleaning and charge values cl = (Phi, Psi, Q) of the cell
 __device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo<double>& m, const RecIn& k,
-                                              const double* U, const double* x, const double* Ec, double* P) {
+                                              const double* cl, const double* x, const double* Ec, double* P) {
     const double* v = x + 1;
     double vl[3];
     lower(m.g, v, vl);
@@ -588,7 +588,7 @@ __device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo
         P[(I_B + i) * p.Np + o] = k.Bc[i] * m.isg;
         P[(I_E + i) * p.Np + o] = Ec[i] * m.isg;
     }
-    for (int f = I_PHI; f < NF; ++f) P[f * p.Np + o] = U[f * p.Np + o] * m.isg;
+    for (int f = I_PHI; f < NF; ++f) P[f * p.Np + o] = cl[f - I_PHI] * m.isg;
 }
 
 __device__ __forceinline__ void copy_prims(const Params& p, long o, const double* Pg, double* P) {
@@ -757,31 +757,84 @@ __device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m,
 // gamma of table imex
 __host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560; }
 
+// ---------------------------------------------------------- stage kernels
+// Persistent: one wave per SIMD (the recovery's register footprint allows no
+// more) walks 64-cell chunks q, q + W, ...; the loads of the next chunk are
+// in flight while the current chunk's recovery runs.
+struct StageIn {
+    long o;
+    bool ok;
+    double P[NF], Un[NF], rh[NF], Us[NF], R1[3], R2[3], sg, a, b[3], g[6], K[6];
+};
+
+// STAGE 1: U^n, the (p, v) guess, sigma, metric; 2: + P(1), rhs, R1, K;
+// 3: P(2), U^n, U(2), rhs, R1, R2, metric, K
+template <int STAGE, bool CURVED>
+__device__ __forceinline__ void stage_load(const Params& p, long t, const double* __restrict__ sig,
+                                           const double* __restrict__ Un, const double* __restrict__ Us,
+                                           const double* __restrict__ Ps, const double* __restrict__ R1,
+                                           const double* __restrict__ R2, const double* __restrict__ rhs, StageIn& in) {
+    in.ok = interior_cell(p, t, in.o);
+    if (!in.ok) return;
+    const long Np = p.Np, o = in.o;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) in.Un[f] = Un[f * Np + o];
+    if (STAGE == 1) {
+        in.P[I_P] = Ps[I_P * Np + o];
+        for (int i = 0; i < 3; ++i) in.P[I_V + i] = Ps[(I_V + i) * Np + o];
+    } else {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) in.P[f] = Ps[f * Np + o];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) in.rh[f] = rhs[f * Np + o];
+        for (int i = 0; i < 3; ++i) in.R1[i] = R1[i * Np + o];
+    }
+    if (STAGE == 3) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) in.Us[f] = Us[f * Np + o];
+        for (int i = 0; i < 3; ++i) in.R2[i] = R2[i * Np + o];
+    } else {
+        in.sg = sig[o];
+    }
+    if (CURVED) {
+        in.a = p.alp[o];
+        for (int a = 0; a < 3; ++a) in.b[a] = p.bet ? p.bet[a * Np + o] : 0.0;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) in.g[a] = p.gam[a * Np + o];
+        if (STAGE != 1)
+            for (int a = 0; a < 6; ++a) in.K[a] = p.K ? p.K[a * Np + o] : 0.0;
+    }
+}
+
+template <bool CURVED> __device__ __forceinline__ void stage_geo(const StageIn& in, Geo<double>& m) {
+    if (CURVED) {
+        m.alp = in.a;
+        for (int a = 0; a < 3; ++a) m.bet[a] = in.b[a];
+        for (int a = 0; a < 6; ++a) m.g[a] = in.g[a];
+        geo_finish(m);
+    } else {
+        geo_flat(m);
+    }
+}
+
 // stage 1: E(1) = E^n + gamma dt R_E(U(1)), everything else unchanged
 template <bool CURVED>
-__global__ __launch_bounds__(256) void k_stage1(const Params p, double dt, const double* __restrict__ sig,
-                                                const double* __restrict__ Un, const double* __restrict__ Pg_,
-                                                double* __restrict__ P1, double* __restrict__ R1,
-                                                double* __restrict__ U1, int* __restrict__ status,
-                                                unsigned long long* nfail) {
-    long o;
-    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
-    const long Np = p.Np;
+__device__ __forceinline__ void stage1_cell(const Params& p, double dt, const StageIn& in,
+                                            const double* __restrict__ Pg_, double* __restrict__ P1,
+                                            double* __restrict__ R1, double* __restrict__ U1,
+                                            int* __restrict__ status, unsigned long long* nfail) {
+    const long Np = p.Np, o = in.o;
     Geo<double> m;
-    cell_geo<CURVED>(p, o, m);
+    stage_geo<CURVED>(in, m);
     RecIn k;
-    {
-        double Uc[NF];
-        for (int f = 0; f < NF; ++f) Uc[f] = Un[f * Np + o];
-        rec_setup(p, m, Uc, k);
-        for (int i = 0; i < 3; ++i) k.Es[i] = Uc[I_E + i];
-        if (U1)
-            for (int f = 0; f < NF; ++f)
-                if (f < I_E || f >= I_E + 3) U1[f * Np + o] = Uc[f];
-    }
+    rec_setup(p, m, in.Un, k);
+    for (int i = 0; i < 3; ++i) k.Es[i] = in.Un[I_E + i];
+    if (U1)
+        for (int f = 0; f < NF; ++f)
+            if (f < I_E || f >= I_E + 3) U1[f * Np + o] = in.Un[f];
     const double gdt = GAM_IMEX() * dt;
-    k.cfac = gdt * m.alp * sig[o];
-    double x[4] = {Pg_[I_P * Np + o], Pg_[I_V * Np + o], Pg_[(I_V + 1) * Np + o], Pg_[(I_V + 2) * Np + o]};
+    k.cfac = gdt * m.alp * in.sg;
+    double x[4] = {in.P[I_P], in.P[I_V], in.P[I_V + 1], in.P[I_V + 2]};
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
     __builtin_amdgcn_sched_barrier(0);
@@ -789,7 +842,7 @@ __global__ __launch_bounds__(256) void k_stage1(const Params p, double dt, const
     else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     __builtin_amdgcn_sched_barrier(0);
     if (st >= 0) {
-        write_prims_k(p, o, m, k, Un, x, E, P1);
+        write_prims_k(p, o, m, k, in.Un + I_PHI, x, E, P1);
     } else {
         for (int f = 0; f < NF; ++f) P1[f * Np + o] = Pg_[f * Np + o];
         for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
@@ -802,55 +855,39 @@ __global__ __launch_bounds__(256) void k_stage1(const Params p, double dt, const
 }
 
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
-// divergence of P_s has been accumulated into rhs.  Output rows are written
-// as soon as they are known so that little stays live across the recovery.
+// divergence (with the metric-derivative sources) of P_s is in rhs
 template <int STAGE, bool CURVED>
-__global__ __launch_bounds__(256) void k_update(const Params p, double dt, const double* __restrict__ sig,
-                                                const double* __restrict__ Un, const double* __restrict__ Us,
-                                                const double* __restrict__ Ps, const double* __restrict__ R1,
-                                                const double* __restrict__ R2, const double* __restrict__ rhs,
-                                                double* __restrict__ Uo, double* __restrict__ Po,
-                                                double* __restrict__ Ro, int* __restrict__ status,
-                                                unsigned long long* nfail) {
-    long o;
-    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
-    const long Np = p.Np;
+__device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
+                                            double* __restrict__ Po, double* __restrict__ Ro,
+                                            int* __restrict__ status, unsigned long long* nfail) {
+    const long Np = p.Np, o = in.o;
     Geo<double> m;
-    cell_geo<CURVED>(p, o, m);
+    stage_geo<CURVED>(in, m);
     const double g = GAM_IMEX();
     RecIn k;
-    double x[4];
+    double x[4] = {in.P[I_P], in.P[I_V], in.P[I_V + 1], in.P[I_V + 2]};
+    double cl[3];
     {
         double Y[NF];
         {
-            double Pc[NF], Uc[NF], S[NF];
-            for (int f = 0; f < NF; ++f) Pc[f] = Ps[f * Np + o];
-            prim2con(m, p.G, Pc, Uc);
-            // derivative terms were added by the flux kernels
-            double K[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            if (CURVED && p.K)
-                for (int a = 0; a < 6; ++a) K[a] = p.K[a * Np + o];
-            sources_local<CURVED>(p, m, K, CURVED && p.K, Pc, Uc, S);
-            x[0] = Pc[I_P];
-            x[1] = Pc[I_V];
-            x[2] = Pc[I_V + 1];
-            x[3] = Pc[I_V + 2];
+            double Uc[NF], S[NF];
+            prim2con(m, p.G, in.P, Uc);
+            sources_local<CURVED>(p, m, in.K, CURVED && p.K, in.P, Uc, S);
             if (STAGE == 2) {
-                for (int f = 0; f < NF; ++f) Y[f] = Un[f * Np + o] + dt * (rhs[f * Np + o] + S[f]);
+                for (int f = 0; f < NF; ++f) Y[f] = in.Un[f] + dt * (in.rh[f] + S[f]);
             } else {
                 // U^{n+1} = (U^n + U(2))/2 + dt/2 F(U(2)) + dt/2 (2 gamma R1 + (1 - gamma) R2) on E
-                for (int f = 0; f < NF; ++f)
-                    Y[f] = 0.5 * (Un[f * Np + o] + Us[f * Np + o]) + 0.5 * dt * (rhs[f * Np + o] + S[f]);
-                for (int i = 0; i < 3; ++i)
-                    Y[I_E + i] += 0.5 * dt * (2.0 * g * R1[i * Np + o] + (1.0 - g) * R2[i * Np + o]);
+                for (int f = 0; f < NF; ++f) Y[f] = 0.5 * (in.Un[f] + in.Us[f]) + 0.5 * dt * (in.rh[f] + S[f]);
+                for (int i = 0; i < 3; ++i) Y[I_E + i] += 0.5 * dt * (2.0 * g * in.R1[i] + (1.0 - g) * in.R2[i]);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
         for (int f = 0; f < NF; ++f)
             if (STAGE == 3 || f < I_E || f >= I_E + 3) Uo[f * Np + o] = Y[f];
         rec_setup(p, m, Y, k);
+        for (int i = 0; i < 3; ++i) cl[i] = Y[I_PHI + i];
         if (STAGE == 2)
-            for (int i = 0; i < 3; ++i) k.Es[i] = Y[I_E + i] + dt * (1.0 - 2.0 * g) * R1[i * Np + o];
+            for (int i = 0; i < 3; ++i) k.Es[i] = Y[I_E + i] + dt * (1.0 - 2.0 * g) * in.R1[i];
         else
             for (int i = 0; i < 3; ++i) k.Es[i] = Y[I_E + i];
     }
@@ -858,7 +895,7 @@ __global__ __launch_bounds__(256) void k_update(const Params p, double dt, const
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
     if (STAGE == 2) {
-        k.cfac = g * dt * m.alp * sig[o];
+        k.cfac = g * dt * m.alp * in.sg;
         if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
         else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     } else {
@@ -866,9 +903,9 @@ __global__ __launch_bounds__(256) void k_update(const Params p, double dt, const
     }
     __builtin_amdgcn_sched_barrier(0);
     if (st >= 0) {
-        write_prims_k(p, o, m, k, Uo, x, E, Po);
+        write_prims_k(p, o, m, k, cl, x, E, Po);
     } else {
-        for (int f = 0; f < NF; ++f) Po[f * Np + o] = Ps[f * Np + o];
+        for (int f = 0; f < NF; ++f) Po[f * Np + o] = in.P[f];
         for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
         atomicAdd(nfail, 1ull);
     }
@@ -879,6 +916,39 @@ __global__ __launch_bounds__(256) void k_update(const Params p, double dt, const
         }
     }
     if (status) status[o] = st;
+}
+
+// STAGE 1: stage1_cell (Us, R2, rhs unused; Ps = the guess, Uo = U1, Ro = R1)
+// STAGE 2, 3: update_cell
+template <int STAGE, bool CURVED>
+__global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const double* __restrict__ sig,
+                                               const double* __restrict__ Un, const double* __restrict__ Us,
+                                               const double* __restrict__ Ps, const double* __restrict__ R1,
+                                               const double* __restrict__ R2, const double* __restrict__ rhs,
+                                               double* __restrict__ Uo, double* __restrict__ Po,
+                                               double* __restrict__ Ro, int* __restrict__ status,
+                                               unsigned long long* nfail) {
+    const long ncell = (long)p.n[0] * p.n[1] * p.n[2];
+    const long nchunk = (ncell + 63) / 64;
+    const long W = (long)gridDim.x * (blockDim.x >> 6);
+    const int lane = threadIdx.x & 63;
+    long q = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (q >= nchunk) return;                                   // uniform per wave
+    StageIn in;
+    stage_load<STAGE, CURVED>(p, q * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, in);
+    for (;;) {
+        const long qn = q + W;
+        StageIn nx;
+        nx.ok = false;
+        if (qn < nchunk) stage_load<STAGE, CURVED>(p, qn * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
+        if (in.ok) {
+            if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Ps, Po, Ro, Uo, status, nfail);
+            else update_cell<STAGE, CURVED>(p, dt, in, Uo, Po, Ro, status, nfail);
+        }
+        if (qn >= nchunk) break;
+        q = qn;
+        in = nx;
+    }
 }
 
 // ---------------------------------------------------- max signal speed (CFL)

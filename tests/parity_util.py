@@ -34,15 +34,19 @@ def rel_errors(gpu, ref, interior, em=True, floor=0.0):
     return np.array(out)
 
 
-def tolerances(nf, base, sigma_max=0.0, dt_over_dx=0.0, n_flux=1):
+def tolerances(nf, base, sigma_max=0.0, dt_over_dx=0.0, n_flux=1, t_total=0.0):
     """Parity bar per field.  Every field gets `base` (1e-12 in FP64) except
     the charge (index 13), whose flux carries J = sigma W [E + v x B - (v.E) v]
     with the bracket a near-cancelling difference of O(|E|) terms: two correct
     FP64 evaluations differ by ~eps sigma |E| per face, i.e. by
-    eps sigma (dt/dx) |E| per flux evaluation, growing like sqrt(n_flux)."""
+    eps sigma (dt/dx) |E| per flux evaluation, growing like sqrt(n_flux); and
+    the E-cleaning scalar Psi (index 12), whose only source coupling to the
+    charge is + alpha Q (alpha <= 1): its deviation is at most the time
+    integral of the charge's, t_total times the charge bar, on top of base."""
     tol = np.full(nf, base)
     if nf == 14:
         tol[13] = max(base, EPS * sigma_max * dt_over_dx * np.sqrt(n_flux))
+        tol[12] = base + t_total * tol[13]
     return tol
 
 

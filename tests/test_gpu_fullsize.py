@@ -125,7 +125,7 @@ def test_curved_256_stage2_sampled(R, orc, recon):
         isR = key == "R2"
         e = rel_errors(got, ref, (slice(None),) * 3, em=not isR, floor=escale if isR else 0.0)
         report(f"256^3 {recon} stage 2 sampled {key} ({len(cells)} cells)", e, names)
-        tol = tolerances(len(e), 1e-12, float(w.sigma.max()), w.dt / w.dx[0], 1)
+        tol = tolerances(len(e), 1e-12, float(w.sigma.max()), w.dt / w.dx[0], 1, t_total=w.dt)
         assert (e <= tol).all(), (key, e)
 
 

@@ -132,7 +132,7 @@ def test_one_step_stagewise_parity(R, orc, name):
         e = rel_errors(gpu[key], ref[key], I, em=not isR, floor=escale if isR else 0.0)
         report(f"{name} {key}", e, names)
         nflux = {"U2": 1, "P2": 1, "R2": 1, "U3": 2, "P3": 2}.get(key, 1)
-        tol = tolerances(len(e), TOL, float(w.sigma.max()), w.dt / min(w.dx), nflux)
+        tol = tolerances(len(e), TOL, float(w.sigma.max()), w.dt / min(w.dx), nflux, t_total=w.dt)
         assert (e <= tol).all(), (key, e, tol)
 
 
@@ -171,7 +171,7 @@ def test_multi_step_parity(R, orc, name, steps):
     eU, eP = rel_errors(U, Uo, I), rel_errors(P, Po, I)
     report(f"{name} {steps} steps U", eU, NAMES_U)
     report(f"{name} {steps} steps P", eP, NAMES_P)
-    tol = tolerances(14, TOL, float(w.sigma.max()), w.dt / min(w.dx), 2 * steps)
+    tol = tolerances(14, TOL, float(w.sigma.max()), w.dt / min(w.dx), 2 * steps, t_total=steps * w.dt)
     assert (eU <= tol).all() and (eP <= tol).all(), (eU, eP, tol)
 
 
@@ -188,7 +188,7 @@ def test_shocktube_full_run_parity(R, orc, seed, sigma0):
     eU, eP = rel_errors(U, Uo, I), rel_errors(P, Po, I)
     report(f"shocktube seed={seed} sigma={sigma0:g} U", eU, NAMES_U)
     report(f"shocktube seed={seed} sigma={sigma0:g} P", eP, NAMES_P)
-    tol = tolerances(14, TOL, sigma0, w.dt / w.dx[0], 2 * w.steps)
+    tol = tolerances(14, TOL, sigma0, w.dt / w.dx[0], 2 * w.steps, t_total=w.steps * w.dt)
     assert (eU <= tol).all() and (eP <= tol).all(), (eU, eP, tol)
 
 
