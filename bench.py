@@ -32,22 +32,30 @@ METRIC = "zone-updates/s per IMEX stage, FP64 vs mixed at 256^3; fwd+adjoint s/s
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
-# Executed FP64 work per interior cell and launch of each kernel class for
-# the 256^3 WENO5 curved workload (from the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
-# counters, FMA = 2 flops, 64 lanes per wave instruction), and algorithmic HBM
-# bytes per interior cell (each word read or written once).
-FLOPS_PER_CELL = {}
+# Per interior cell and launch of each kernel class on the 256^3 curved WENO5
+# workload (zero shift and extrinsic curvature, so the metric read is alpha and
+# gamma_ij, 7 words):
+#  * algorithmic HBM bytes: each word the kernel must read or write, once;
+#  * FP64 flops: executed, from the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
+#    counters (FMA = 2 flops, 64 lanes per wave instruction);
+#  * measured HBM traffic: FETCH_SIZE + WRITE_SIZE of the same launch, scaled by
+#    what the counters read for a streaming kernel of known size.
+# The flops and traffic figures belong to the kernels as profiled (the file
+# names under profiles/ say which); they are re-measured when a kernel changes.
 BYTES_PER_CELL = {
-    # P 14 + metric alpha, gamma 7 + sigma 1 read, rhs 14 written
-    "flux_x": 8 * (14 + 7 + 1 + 14),
-    # as x, plus the read-modify-write of rhs
-    "flux_y": 8 * (14 + 7 + 1 + 14 + 14),
-    "flux_z": 8 * (14 + 7 + 1 + 14 + 14),
-    # rhs 14, U^n 14, P(1) 14, R1 3, sigma 1, metric 7 read; U(2) 14, P(2) 14, R2 3 written
+    # P 14 + sigma 1 + metric 7 read, rhs 14 written
+    "flux_x": 8 * (14 + 1 + 7 + 14),
+    # as x, plus the read half of the rhs read-modify-write
+    "flux_y": 8 * (14 + 1 + 7 + 14 + 14),
+    "flux_z": 8 * (14 + 1 + 7 + 14 + 14),
+    # P(1) 14, U^n 14, rhs 14, R1 3, sigma 1, metric 7 read; U(2) 14, P(2) 14, R2 3 written
     "update_stage2": 8 * (14 + 14 + 14 + 3 + 1 + 7 + 14 + 14 + 3),
-    # ghost faces only
+    # ghost layers only
     "ghost_fill": 0,
 }
+FLOPS_PER_CELL = {"flux_x": 3257.6, "flux_y": 2790.8, "flux_z": 2792.8, "update_stage2": 2659.4}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 210.9 + 117.6, "flux_y": 375.5 + 148.1, "flux_z": 377.0 + 155.6,
+                          "update_stage2": 567.5 + 265.4}
 
 
 def parse():
@@ -106,6 +114,31 @@ def cpu_baseline(w, dt, sample, reps):
             "sample": f"{reps} applications of IMEX stage 2 on the central {nx}x{ny}x{nz} cells of the 256^3 "
                       f"curved-blob workload (real neighbour ghosts, held fixed), after two oracle steps; "
                       f"{t:.2f} s timed, {int(s2['nfail'])} failed cells"}
+
+
+def roofline(per_launch, kern, ncell):
+    """Roofline of the kernel class with the largest total time: its binding
+    ceiling is the larger of the HBM time of its algorithmic bytes and the FP64
+    time of its flops; both fractions are reported."""
+    dominant = max(per_launch, key=lambda k: kern[k][0])
+    t = per_launch[dominant] * 1e-3
+    nbytes = BYTES_PER_CELL.get(dominant, 0) * ncell
+    flops = FLOPS_PER_CELL.get(dominant, 0.0) * ncell
+    t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+    t_alu = flops / (PEAK_FP64_VECTOR_TFLOPS * 1e12)
+    gbs = nbytes / t / 1e9
+    tfs = flops / t / 1e12
+    traffic = TRAFFIC_BYTES_PER_CELL.get(dominant)
+    if t_alu > t_hbm:
+        roof = {"bound": "alu", "achieved": tfs, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                "frac": tfs / PEAK_FP64_VECTOR_TFLOPS}
+    else:
+        roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
+    roof["traffic"] = None if traffic is None else traffic * ncell / 1e9
+    roof.update({"traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, calibrated)", "kernel": dominant,
+                 "kernel_ms": t * 1e3, "algorithmic_GB": nbytes / 1e9, "hbm_frac": gbs / PEAK_HBM_GBS,
+                 "fp64_TFLOP": flops / 1e12, "fp64_frac": tfs / PEAK_FP64_VECTOR_TFLOPS})
+    return roof
 
 
 def adjoint_leg(torch, rmhd, W, steps):
@@ -242,10 +275,12 @@ def main():
         raise SystemExit("failed recoveries in the full steps")
 
     if args.calibrate_copy:
-        a = torch.empty(1 << 28, dtype=torch.float64, device="cuda")   # 2 GiB
+        # a plain streaming kernel of known traffic for the HBM byte counters:
+        # b = -a over 2^28 doubles reads 2 GiB and writes 2 GiB
+        a = torch.zeros(1 << 28, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
         for _ in range(2):
-            b.copy_(a)
+            torch.neg(a, out=b)
         torch.cuda.synchronize()
         del a, b
 
@@ -290,20 +325,13 @@ def main():
         adjoint = adjoint_leg(torch, rmhd, W, args.adjoint_steps)
 
     per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
-    dominant = max(per_launch, key=lambda k: kern[k][0])
-    dom_ms = per_launch[dominant]
-    if dominant in FLOPS_PER_CELL:
-        flops = FLOPS_PER_CELL[dominant] * ncell
-        achieved = flops / (dom_ms * 1e-3) / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP64_VECTOR_TFLOPS, "traffic": None, "kernel": dominant}
-    else:
-        bytes_ = BYTES_PER_CELL.get(dominant, 0) * ncell
-        achieved = bytes_ / (dom_ms * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": None, "kernel": dominant}
-    roof["kernel_ms"] = dom_ms
-    roof["hbm_gbs_algorithmic"] = BYTES_PER_CELL.get(dominant, 0) * ncell / (dom_ms * 1e-3) / 1e9
+    roof = roofline(per_launch, kern, ncell)
+    stage_bytes = sum(BYTES_PER_CELL.get(k, 0) * kern[k][1] for k in kern) / max(1, args.steps) * ncell
+    stage_flops = sum(FLOPS_PER_CELL.get(k, 0.0) * kern[k][1] for k in kern) / max(1, args.steps) * ncell
+    roof["stage"] = {"ms": ms / args.steps, "algorithmic_GB": stage_bytes / 1e9,
+                     "hbm_frac": stage_bytes / (ms / args.steps * 1e-3) / 1e9 / PEAK_HBM_GBS,
+                     "fp64_TFLOP": stage_flops / 1e12,
+                     "fp64_frac": stage_flops / (ms / args.steps * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS}
 
     cpu = None
     if not args.no_cpu_baseline:
