@@ -319,21 +319,32 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
 }
 
 // ------------------------------------------- y / z fluxes: rolling window
-// Lanes along x (coalesced 512-byte rows), one wave marches a segment of
-// cells along D.  Every row of P and sigma is loaded once, into a per-lane
-// ring of the last five rows in LDS (38.4 KB per wave); the metric rows of
-// the window (c-3 .. c+2) stay in registers.  Step c: reconstruct c from rows
-// c-2..c+2 and take its current; face c-1/2 from the carried right state of
-// c-1 and the left state of c; rhs of c-1 = rhs + its sources (derivatives
-// from rows c-3..c+1) - the flux difference.  Lanes never exchange data.
-constexpr int WRING = 5, WNF = NF + 1;   // ring slots, fields per slot (P + sigma)
+// Lanes along x, one wave marches a segment of cells along D.  Every row of P
+// is loaded once, straight from HBM into a ring of the last five rows in LDS
+// (global_load_lds_dwordx4: lane m brings two consecutive doubles of one of
+// two fields, so one instruction fills two 64-wide field rows; 35.8 KB per
+// wave); the metric and sigma rows of the window (c-3 .. c+2) stay in
+// registers.  Step c: rhs row c-1 is read, its sources are formed
+// (derivatives from rows c-3..c+1), the current and the reconstruction of c
+// are taken; then row c+3 is requested into the ring slot that row c-2 has
+// just left, and while it arrives the face c-1/2 is computed and rhs row c-1
+// written.  Lanes exchange data only through the ring.
+constexpr int WRING = 5;
+
+// all counters but vmcnt at their maxima: wait for every outstanding vector
+// memory operation, including the ring loads into LDS
+__device__ __forceinline__ void wait_ring() {
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
 
 template <int D, int RECON, bool CURVED, class R>
 __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __restrict__ P,
                                                const double* __restrict__ sig, double* __restrict__ rhs,
                                                int seglen, int nxb, int nseg) {
     constexpr int E = (D == 1) ? 2 : 1;                 // the other transverse dimension
-    __shared__ double ring[WRING * WNF * 64];
+    __shared__ double ring[WRING * NF * 64];
     const int lane = threadIdx.x;
     const long wid = xcd_block();
     if (wid >= (long)nxb * p.n[E] * nseg) return;      // uniform per wave
@@ -342,80 +353,86 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     const int e = (int)(r % p.n[E]);
     const int seg = (int)(r / p.n[E]);
     const int i = xb * 64 + lane;
-    if (i >= p.n[0]) return;                            // lanes are independent
+    const bool valid = i < p.n[0];                      // every lane takes part in the ring loads
     const int nD = p.n[D], gD = p.g[D];
     const int c0 = seg * seglen, c1 = min(c0 + seglen, nD);
     const long s = p.st[D], Np = p.Np;
-    const long base = (long)(i + p.g[0]) + (long)(e + p.g[E]) * p.st[E];
+    const long rowb = (long)(e + p.g[E]) * p.st[E];    // row offset without x and D
+    const long base = rowb + (i < p.n[0] ? i : p.n[0] - 1) + p.g[0];
+    // ring loads: lane m carries x pair 2(m mod 32) of field f + m / 32, clamped into the padded row
+    const long xpair = min((long)p.g[0] + (long)xb * 64 + 2 * (lane & 31), (long)p.np[0] - 2);
+    const int fhalf = lane >> 5;
     const R ih = R(p.idx[D]);
     const double cd = p.idx[D] / 12.0;
-    double* rw = ring + lane;
-    auto ringP = [&](int c, int f) -> double& { return rw[(((c + gD) % WRING) * WNF + f) * 64]; };
-
-    // metric window, index k <-> row c - 3 + k
-    double wa[6], wb[6][3], wg[6][6];
-    auto load_metric = [&](int c, double& ar, double* br, double* gr) {
-        const long o = base + (long)(c + gD) * s;
-        ar = p.alp[o];
-        for (int a = 0; a < 3; ++a) br[a] = p.bet ? p.bet[a * Np + o] : 0.0;
-#pragma unroll
-        for (int a = 0; a < 6; ++a) gr[a] = p.gam[a * Np + o];
-    };
+    auto slot = [&](int c) { return (c + gD) % WRING; };
+    auto ringP = [&](int c, int f) -> double { return ring[(slot(c) * NF + f) * 64 + lane]; };
     auto load_ring = [&](int c) {
-        const long o = base + (long)(c + gD) * s;
+        const double* src = P + (long)fhalf * Np + rowb + (long)(c + gD) * s + xpair;
+        double* dst = ring + slot(c) * NF * 64;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) ringP(c, f) = P[f * Np + o];
-        ringP(c, NF) = sig[o + (long)(bc_map(p, D, c + gD) - (c + gD)) * s];
+        for (int f = 0; f < NF; f += 2)
+            __builtin_amdgcn_global_load_lds((const void*)(src + (long)f * Np),
+                                             (__attribute__((address_space(3))) void*)(dst + f * 64), 16, 0, 0);
+    };
+
+    // metric and sigma window, index k <-> row c - 3 + k
+    double wa[6], wb[6][3], wg[6][6], ws[6];
+    auto load_metric = [&](int c, double& ar, double* br, double* gr, double& sr) {
+        const long o = base + (long)(c + gD) * s;
+        sr = sig[o + (long)(bc_map(p, D, c + gD) - (c + gD)) * s];
+        if (CURVED) {
+            ar = p.alp[o];
+            for (int a = 0; a < 3; ++a) br[a] = p.bet ? p.bet[a * Np + o] : 0.0;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) gr[a] = p.gam[a * Np + o];
+        }
     };
     // window of the first step (c = c0 - 1): P rows c0-3 .. c0+1, metric rows
     // c0-4 .. c0+1 (row c0-4 is outside the padding when c0 = 0 and unused)
     for (int c = c0 - 3; c <= c0 + 1; ++c) load_ring(c);
-    if (CURVED) {
-        for (int k = 0; k < 6; ++k) {
-            const int c = c0 - 4 + k;
-            if (c >= -gD) {
-                load_metric(c, wa[k], wb[k], wg[k]);
-            } else {
-                wa[k] = 0.0;
-                for (int a = 0; a < 3; ++a) wb[k][a] = 0.0;
-                for (int a = 0; a < 6; ++a) wg[k][a] = 0.0;
-            }
-        }
+    for (int k = 0; k < 6; ++k) {
+        const int c = c0 - 4 + k;
+        wa[k] = 0.0;
+        ws[k] = 0.0;
+        for (int a = 0; a < 3; ++a) wb[k][a] = 0.0;
+        for (int a = 0; a < 6; ++a) wg[k][a] = 0.0;
+        if (c >= -gD) load_metric(c, wa[k], wb[k], wg[k], ws[k]);
     }
 
     R PLc[NF], Fprev[NF];
     double Jprev = 0.0;
 #pragma unroll 1
     for (int c = c0 - 1; c <= c1; ++c) {
+        const bool more = c < c1;
+        // metric and sigma of row c + 3, in flight during the step
+
         const bool fin = c - 1 >= c0;                   // rhs of c - 1 is finished this step
         const long om = base + (long)(c - 1 + gD) * s;
         double acc[NF];
         if (fin) {
 #pragma unroll
             for (int f = 0; f < NF; ++f) acc[f] = rhs[f * Np + om];
-            if (CURVED) {
-                // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
-                Geo<double> ms;
-                ms.alp = wa[2];
-                for (int a = 0; a < 3; ++a) ms.bet[a] = wb[2][a];
-                for (int a = 0; a < 6; ++a) ms.g[a] = wg[2][a];
-                geo_finish(ms);
-                auto d4 = [&](double a0, double a1, double a3, double a4) {
-                    return (a0 - 8.0 * a1 + 8.0 * a3 - a4) * cd;
-                };
-                const double da = d4(wa[0], wa[1], wa[3], wa[4]);
-                double db[3], dg[6];
-                for (int a = 0; a < 3; ++a) db[a] = d4(wb[0][a], wb[1][a], wb[3][a], wb[4][a]);
-                for (int a = 0; a < 6; ++a) dg[a] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
-                double Pm[NF], Um[NF];
+        }
+        if (fin && CURVED) {
+            // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
+            Geo<double> ms;
+            ms.alp = wa[2];
+            for (int a = 0; a < 3; ++a) ms.bet[a] = wb[2][a];
+            for (int a = 0; a < 6; ++a) ms.g[a] = wg[2][a];
+            geo_finish(ms);
+            auto d4 = [&](double a0, double a1, double a3, double a4) { return (a0 - 8.0 * a1 + 8.0 * a3 - a4) * cd; };
+            const double da = d4(wa[0], wa[1], wa[3], wa[4]);
+            double db[3], dg[6];
+            for (int a = 0; a < 3; ++a) db[a] = d4(wb[0][a], wb[1][a], wb[3][a], wb[4][a]);
+            for (int a = 0; a < 6; ++a) dg[a] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
+            double Pm[NF], Um[NF];
 #pragma unroll
-                for (int f = 0; f < NF; ++f) Pm[f] = ringP(c - 1, f);
-                prim2con(ms, p.G, Pm, Um);
-                sources_dir<D>(p, ms, da, db, dg, Pm, Um, acc);
-            }
+            for (int f = 0; f < NF; ++f) Pm[f] = ringP(c - 1, f);
+            prim2con(ms, p.G, Pm, Um);
+            sources_dir<D>(p, ms, da, db, dg, Pm, Um, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
-        // current of c (metric row c: window 3)
+        // current of c (metric and sigma row c: window 3)
         double Jc;
         {
             Geo<double> mc;
@@ -430,10 +447,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             double Pc[NF], J[3];
 #pragma unroll
             for (int f = 0; f < NF; ++f) Pc[f] = ringP(c, f);
-            current(mc, Pc, ringP(c, NF), J);
+            current(mc, Pc, ws[3], J);
             Jc = J[D];
         }
-        __builtin_amdgcn_sched_barrier(0);
+        // ring row c + 2 (requested last step) must have landed
+        wait_ring();
         // reconstruction of c
         R fm[NF], fp[NF];
 #pragma unroll
@@ -444,7 +462,10 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                              R(ringP(c + 1, f + sl)), R(ringP(c + 2, f + sl))};
             recon<RECON>(st, fm[f], fp[f]);
         }
+        // row c - 2 is consumed: request row c + 3 into its slot
         __builtin_amdgcn_sched_barrier(0);
+        asm volatile("" ::: "memory");
+        if (more) load_ring(c + 3);
         if (c >= c0) {
             // face c - 1/2: metric at the face from rows c-2 .. c+1 (window 1..4)
             Geo<R> m;
@@ -460,15 +481,15 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                 geo_flat(m);
             }
             if (bad_state(m, PLc))
-                for (int f = 0; f < NF; ++f) PLc[f] = R(ringP(c - 1, f));
+                for (int f = 0; f < NF; ++f) PLc[f] = R(P[f * Np + base + (long)(c - 1 + gD) * s]);
             R PR[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) PR[f] = fm[f];
             if (bad_state(m, PR))
-                for (int f = 0; f < NF; ++f) PR[f] = R(ringP(c, f));
+                for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + base + (long)(c + gD) * s]);
             R Fh[NF];
             face_flux<D>(p, m, PLc, PR, R(0.5 * (Jprev + Jc)), Fh);
-            if (fin) {
+            if (fin && valid) {
 #pragma unroll
                 for (int f = 0; f < NF; ++f) rhs[f * Np + om] = acc[f] + double(-(Fh[f] - Fprev[f]) * ih);
             }
@@ -478,20 +499,27 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
 #pragma unroll
         for (int f = 0; f < NF; ++f) PLc[f] = fp[f];
         Jprev = Jc;
-        // advance the window by one row
-        if (c < c1) {
-            load_ring(c + 3);
-            if (CURVED) {
+        // advance the register window by one row
+        if (more) {
+            double an = 0.0, bn[3] = {0.0, 0.0, 0.0}, gn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, sn = 0.0;
+            load_metric(c + 3, an, bn, gn, sn);
 #pragma unroll
-                for (int k = 0; k < 5; ++k) {
+            for (int k = 0; k < 5; ++k) {
+                ws[k] = ws[k + 1];
+                if (CURVED) {
                     wa[k] = wa[k + 1];
                     for (int a = 0; a < 3; ++a) wb[k][a] = wb[k + 1][a];
                     for (int a = 0; a < 6; ++a) wg[k][a] = wg[k + 1][a];
                 }
-                load_metric(c + 3, wa[5], wb[5], wg[5]);
             }
+            ws[5] = sn;
+            wa[5] = an;
+            for (int a = 0; a < 3; ++a) wb[5][a] = bn[a];
+            for (int a = 0; a < 6; ++a) wg[5][a] = gn[a];
         }
     }
+    // no ring load may be in flight when the wave ends
+    wait_ring();
 }
 
 // ---------------------------------------------------------------- ghost fill
