@@ -124,7 +124,9 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
  * centres including ghosts, layouts above).  beta == NULL means zero shift,
  * K == NULL zero extrinsic curvature; alpha == NULL and gamma == NULL restore
  * flat space.  The arrays are referenced, not copied: keep them alive and
- * unchanged while the context uses them. */
+ * unchanged while the context uses them.  A beta or K that is zero in every
+ * cell is treated as NULL (checked here on the device; the call synchronises
+ * the stream when beta or K is given). */
 int rmhd_set_metric(rmhd_ctx* ctx, const double* alpha, const double* beta, const double* gamma, const double* K);
 
 /* Conserved from primitive variables, eqs. conserved_dens, conserved_tau,

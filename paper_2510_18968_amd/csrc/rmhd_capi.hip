@@ -21,7 +21,7 @@ struct rmhd_ctx {
     char* ws;
     size_t ws_bytes;
     double *rhs, *P1, *R1, *U2, *P2, *R2;
-    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits
+    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits, [2] metric scan flag
     bool curved;
     long persist_blocks = 256;   // persistent flux grid: one 4-wave block per CU, multiple of 8
     // opt-in launch timing: event pairs per kernel class, reused after a read
@@ -166,7 +166,10 @@ template <int D, int RECON, bool CURVED, class R> void flux_w(rmhd_ctx* c, const
     const int nxb = (p.n[0] + 63) / 64, nseg = (p.n[D] + seglen - 1) / seglen;
     const long waves = (long)nxb * p.n[E] * nseg;
     const long blocks = (waves + 7) / 8 * 8;          // one wave per block; multiple of 8 for the XCD renumbering
-    k_flux_w<D, RECON, CURVED, R><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+    if (CURVED && p.bet)
+        k_flux_w<D, RECON, CURVED, R, true><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+    else
+        k_flux_w<D, RECON, CURVED, R, false><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
 }
 
 template <int RECON, bool CURVED, class R> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
@@ -465,10 +468,26 @@ int rmhd_set_metric(rmhd_ctx* c, const double* alpha, const double* beta, const 
     if (!c) return fail(RMHD_EINVAL, "null context");
     if ((alpha == nullptr) != (gamma == nullptr)) return fail(RMHD_EINVAL, "alpha and gamma must both be set or both null");
     if (!alpha && (beta || K)) return fail(RMHD_EINVAL, "beta/K need alpha and gamma");
+    // a shift or extrinsic curvature that is zero everywhere is dropped, which
+    // selects the kernels without those terms (fewer registers and loads)
+    auto all_zero = [&](const double* a, long n, bool& zero) -> int {
+        k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters + 2, 1);
+        k_any_nonzero<<<(unsigned)std::min<long>(nblk(n, 256), 4096), 256, 0, c->stream>>>(a, n, c->counters + 2);
+        LAUNCH_CHECK();
+        unsigned long long h = 0;
+        HIP_TRY(hipMemcpyAsync(&h, c->counters + 2, sizeof h, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        zero = h == 0;
+        return RMHD_OK;
+    };
+    bool zb = false, zk = false;
+    int r;
+    if (beta && (r = all_zero(beta, 3 * c->p.Np, zb)) != RMHD_OK) return r;
+    if (K && (r = all_zero(K, 6 * c->p.Np, zk)) != RMHD_OK) return r;
     c->p.alp = alpha;
     c->p.gam = gamma;
-    c->p.bet = beta;
-    c->p.K = K;
+    c->p.bet = (beta && !zb) ? beta : nullptr;
+    c->p.K = (K && !zk) ? K : nullptr;
     c->curved = alpha != nullptr;
     return RMHD_OK;
 }

@@ -339,7 +339,9 @@ __device__ __forceinline__ void wait_ring() {
     asm volatile("" ::: "memory");
 }
 
-template <int D, int RECON, bool CURVED, class R>
+// SHIFT: the metric has a shift (beta rows in the window); without one the
+// window holds alpha, gamma_ij and sigma only
+template <int D, int RECON, bool CURVED, class R, bool SHIFT>
 __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __restrict__ P,
                                                const double* __restrict__ sig, double* __restrict__ rhs,
                                                int seglen, int nxb, int nseg) {
@@ -376,13 +378,15 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     };
 
     // metric and sigma window, index k <-> row c - 3 + k
-    double wa[6], wb[6][3], wg[6][6], ws[6];
+    double wa[6], wb[SHIFT ? 6 : 1][3], wg[6][6], ws[6];
+    auto bw = [&](int k, int a) { return SHIFT ? wb[SHIFT ? k : 0][a] : 0.0; };
     auto load_metric = [&](int c, double& ar, double* br, double* gr, double& sr) {
         const long o = base + (long)(c + gD) * s;
         sr = sig[o + (long)(bc_map(p, D, c + gD) - (c + gD)) * s];
         if (CURVED) {
             ar = p.alp[o];
-            for (int a = 0; a < 3; ++a) br[a] = p.bet ? p.bet[a * Np + o] : 0.0;
+            if (SHIFT)
+                for (int a = 0; a < 3; ++a) br[a] = p.bet[a * Np + o];
 #pragma unroll
             for (int a = 0; a < 6; ++a) gr[a] = p.gam[a * Np + o];
         }
@@ -394,9 +398,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         const int c = c0 - 4 + k;
         wa[k] = 0.0;
         ws[k] = 0.0;
-        for (int a = 0; a < 3; ++a) wb[k][a] = 0.0;
+        double bdummy[3];
+        double* bk = SHIFT ? wb[SHIFT ? k : 0] : bdummy;
+        for (int a = 0; a < 3; ++a) bk[a] = 0.0;
         for (int a = 0; a < 6; ++a) wg[k][a] = 0.0;
-        if (c >= -gD) load_metric(c, wa[k], wb[k], wg[k], ws[k]);
+        if (c >= -gD) load_metric(c, wa[k], bk, wg[k], ws[k]);
     }
 
     R PLc[NF], Fprev[NF];
@@ -417,13 +423,13 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
             Geo<double> ms;
             ms.alp = wa[2];
-            for (int a = 0; a < 3; ++a) ms.bet[a] = wb[2][a];
+            for (int a = 0; a < 3; ++a) ms.bet[a] = bw(2, a);
             for (int a = 0; a < 6; ++a) ms.g[a] = wg[2][a];
             geo_finish(ms);
             auto d4 = [&](double a0, double a1, double a3, double a4) { return (a0 - 8.0 * a1 + 8.0 * a3 - a4) * cd; };
             const double da = d4(wa[0], wa[1], wa[3], wa[4]);
             double db[3], dg[6];
-            for (int a = 0; a < 3; ++a) db[a] = d4(wb[0][a], wb[1][a], wb[3][a], wb[4][a]);
+            for (int a = 0; a < 3; ++a) db[a] = d4(bw(0, a), bw(1, a), bw(3, a), bw(4, a));
             for (int a = 0; a < 6; ++a) dg[a] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
             double Pm[NF], Um[NF];
 #pragma unroll
@@ -438,7 +444,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             Geo<double> mc;
             if (CURVED) {
                 mc.alp = wa[3];
-                for (int a = 0; a < 3; ++a) mc.bet[a] = wb[3][a];
+                for (int a = 0; a < 3; ++a) mc.bet[a] = bw(3, a);
                 for (int a = 0; a < 6; ++a) mc.g[a] = wg[3][a];
                 geo_finish(mc);
             } else {
@@ -474,7 +480,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                     return (-a0 + 9.0 * a1 + 9.0 * a2 - a3) * 0.0625;
                 };
                 m.alp = R(f4(wa[1], wa[2], wa[3], wa[4]));
-                for (int a = 0; a < 3; ++a) m.bet[a] = R(f4(wb[1][a], wb[2][a], wb[3][a], wb[4][a]));
+                for (int a = 0; a < 3; ++a) m.bet[a] = R(f4(bw(1, a), bw(2, a), bw(3, a), bw(4, a)));
                 for (int a = 0; a < 6; ++a) m.g[a] = R(f4(wg[1][a], wg[2][a], wg[3][a], wg[4][a]));
                 geo_finish(m);
             } else {
@@ -508,18 +514,29 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                 ws[k] = ws[k + 1];
                 if (CURVED) {
                     wa[k] = wa[k + 1];
-                    for (int a = 0; a < 3; ++a) wb[k][a] = wb[k + 1][a];
+                    if (SHIFT)
+                        for (int a = 0; a < 3; ++a) wb[SHIFT ? k : 0][a] = wb[SHIFT ? k + 1 : 0][a];
                     for (int a = 0; a < 6; ++a) wg[k][a] = wg[k + 1][a];
                 }
             }
             ws[5] = sn;
             wa[5] = an;
-            for (int a = 0; a < 3; ++a) wb[5][a] = bn[a];
+            if (SHIFT)
+                for (int a = 0; a < 3; ++a) wb[SHIFT ? 5 : 0][a] = bn[a];
             for (int a = 0; a < 6; ++a) wg[5][a] = gn[a];
         }
     }
     // no ring load may be in flight when the wave ends
     wait_ring();
+}
+
+// ------------------------------------------------ metric set-up (one-time)
+// flag := 1 if any of a[0..n) is non-zero (wave vote, one atomic per wave)
+__global__ void k_any_nonzero(const double* __restrict__ a, long n, unsigned long long* flag) {
+    bool nz = false;
+    for (long t = (long)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x)
+        nz = nz || a[t] != 0.0;
+    if (__any(nz) && (threadIdx.x & 63) == 0) atomicOr(flag, 1ull);
 }
 
 // ---------------------------------------------------------------- ghost fill

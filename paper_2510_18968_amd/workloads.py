@@ -205,13 +205,17 @@ def periodic_box(n=128, seed=201, cfl=0.4, steps=10) -> Workload:
 
 
 # ----------------------------------------------------------------- config 3
-def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20) -> Workload:
+def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20, shift=0.0) -> Workload:
     """Static conformally flat background on [-1,1]^3 (gamma_ij = psi^4
     delta_ij, psi = 1 + 0.1 exp(-r^2/0.25), alpha = 1 - 0.3 exp(-r^2/0.25),
     zero shift and extrinsic curvature), a seeded density blob
     rho = 1e-3 + exp(-r^2/0.09)(1 + 0.05 noise), p = 100 rho^2, v = E = 0,
     a poloidal B (max |B| = 1e-3) confined to r < 0.4 from the discrete curl
-    of A = a(r) (-y, x, 0), and sigma = 1e6 rho/rho_max + 1; Gamma = 2."""
+    of A = a(r) (-y, x, 0), and sigma = 1e6 rho/rho_max + 1; Gamma = 2.
+    shift != 0 adds a smooth shift beta = shift b(r) (y, -x, z/2) and
+    extrinsic curvature K_ij = shift b(r) k_ij (fixed symmetric k), b the bump,
+    to exercise every metric term (input fields, not a solution of Einstein's
+    equations)."""
     rng = np.random.default_rng(seed)
     dx = 2.0 / n
     nn = (n, n, n)
@@ -224,6 +228,10 @@ def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20) -> Workload:
     psi = 1.0 + 0.1 * bump
     met[0] = 1.0 - 0.3 * bump
     met[4] = met[7] = met[9] = psi ** 4
+    if shift:
+        met[1], met[2], met[3] = shift * bump * y, -shift * bump * x, 0.5 * shift * bump * z
+        for a, kv in enumerate((1.0, 0.2, -0.1, 0.8, 0.3, 0.5)):
+            met[10 + a] = shift * kv * bump
     noise = _pad(rng.uniform(-1.0, 1.0, (n, n, n)), nn, 7, "edge")
     P = np.zeros((14,) + shape)
     P[0] = 1e-3 + np.exp(-r2 / 0.09) * (1.0 + 0.05 * noise)
@@ -255,7 +263,7 @@ def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20) -> Workload:
     P[5], P[6], P[7] = Bx * scale, By * scale, Bz * scale
     rho_max = float(P[0][inner].max())
     sigma = 1e6 * P[0] / rho_max + 1.0
-    return Workload(f"curved_blob_{n}^3_{recon}", nn, 7, (dx,) * 3, (x0,) * 3, (1, 1, 1), 2.0, RECON[recon],
+    return Workload(f"curved_blob_{n}^3_{recon}" + ("_shift" if shift else ""), nn, 7, (dx,) * 3, (x0,) * 3, (1, 1, 1), 2.0, RECON[recon],
                     cfl * dx, steps, P, sigma, met, extra=dict(seed=seed, cfl=cfl))
 
 

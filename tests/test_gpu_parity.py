@@ -42,10 +42,11 @@ def small_workloads():
         "blob20_mc2": W.curved_blob(n=20, recon="mc2", steps=2),
         "blob20_minmod": W.curved_blob(n=20, recon="minmod", steps=2),
         "batch4x128": W.sheet_batch(nprob=4, n=128, steps=3),
+        "blob16_shift_weno5": W.curved_blob(n=16, recon="weno5", steps=2, shift=0.05),
     }
 
 
-@pytest.mark.parametrize("name", ["box12", "blob20_weno5"])
+@pytest.mark.parametrize("name", ["box12", "blob20_weno5", "blob16_shift_weno5"])
 def test_prim2con_parity(R, orc, name):
     w = small_workloads()[name]
     g = R.grid_for(w)
@@ -161,7 +162,8 @@ def run_oracle(orc, w, steps):
 
 
 @pytest.mark.parametrize("name,steps", [("box12", 2), ("blob20_weno5", 2), ("blob20_mc2", 2),
-                                        ("batch4x128", 3), ("shocktube_s1", 20), ("shocktube_s1e6", 20)])
+                                        ("batch4x128", 3), ("shocktube_s1", 20), ("shocktube_s1e6", 20),
+                                        ("blob16_shift_weno5", 3)])
 def test_multi_step_parity(R, orc, name, steps):
     w = small_workloads()[name]
     U, P, nf = run_gpu(R, w, steps)
