@@ -217,12 +217,15 @@ int launch_stage(rmhd_ctx* c, double dt, const double* sig, const double* Un, co
                  const double* R1, const double* R2, double* Uo, double* Po, double* Ro, int32_t* st) {
     const long nchunk = (ncells(c->p) + 63) / 64;
     const long blocks = std::max<long>(1, std::min<long>(c->persist_blocks, (nchunk + 3) / 4));
-    if (c->curved)
-        k_stage<STAGE, true><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po, Ro,
-                                                             st, c->counters);
+    if (c->curved && c->p.K)
+        k_stage<STAGE, true, true><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                   Ro, st, c->counters);
+    else if (c->curved)
+        k_stage<STAGE, true, false><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                    Ro, st, c->counters);
     else
-        k_stage<STAGE, false><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po, Ro,
-                                                              st, c->counters);
+        k_stage<STAGE, false, false><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                     Ro, st, c->counters);
     LAUNCH_CHECK();
     return RMHD_OK;
 }

@@ -809,12 +809,12 @@ __host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560;
 struct StageIn {
     long o;
     bool ok;
-    double P[NF], Un[NF], rh[NF], Us[NF], R1[3], R2[3], sg, a, b[3], g[6], K[6];
+    double P[NF], Un[NF], rh[NF], Us[NF], R1[3], R2[3], sg, a, g[6], K[6];
 };
 
 // STAGE 1: U^n, the (p, v) guess, sigma, metric; 2: + P(1), rhs, R1, K;
 // 3: P(2), U^n, U(2), rhs, R1, R2, metric, K
-template <int STAGE, bool CURVED>
+template <int STAGE, bool CURVED, bool HASK>
 __device__ __forceinline__ void stage_load(const Params& p, long t, const double* __restrict__ sig,
                                            const double* __restrict__ Un, const double* __restrict__ Us,
                                            const double* __restrict__ Ps, const double* __restrict__ R1,
@@ -843,18 +843,18 @@ __device__ __forceinline__ void stage_load(const Params& p, long t, const double
     }
     if (CURVED) {
         in.a = p.alp[o];
-        for (int a = 0; a < 3; ++a) in.b[a] = p.bet ? p.bet[a * Np + o] : 0.0;
 #pragma unroll
         for (int a = 0; a < 6; ++a) in.g[a] = p.gam[a * Np + o];
-        if (STAGE != 1)
-            for (int a = 0; a < 6; ++a) in.K[a] = p.K ? p.K[a * Np + o] : 0.0;
+        if (STAGE != 1 && HASK)
+            for (int a = 0; a < 6; ++a) in.K[a] = p.K[a * Np + o];
     }
 }
 
+// (the shift enters the stage kernels nowhere: the flux kernels carry it)
 template <bool CURVED> __device__ __forceinline__ void stage_geo(const StageIn& in, Geo<double>& m) {
     if (CURVED) {
         m.alp = in.a;
-        for (int a = 0; a < 3; ++a) m.bet[a] = in.b[a];
+        for (int a = 0; a < 3; ++a) m.bet[a] = 0.0;
         for (int a = 0; a < 6; ++a) m.g[a] = in.g[a];
         geo_finish(m);
     } else {
@@ -901,7 +901,7 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
 
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
 // divergence (with the metric-derivative sources) of P_s is in rhs
-template <int STAGE, bool CURVED>
+template <int STAGE, bool CURVED, bool HASK>
 __device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
                                             double* __restrict__ Po, double* __restrict__ Ro,
                                             int* __restrict__ status, unsigned long long* nfail) {
@@ -917,7 +917,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
         {
             double Uc[NF], S[NF];
             prim2con(m, p.G, in.P, Uc);
-            sources_local<CURVED>(p, m, in.K, CURVED && p.K, in.P, Uc, S);
+            sources_local<CURVED>(p, m, in.K, CURVED && HASK, in.P, Uc, S);
             if (STAGE == 2) {
                 for (int f = 0; f < NF; ++f) Y[f] = in.Un[f] + dt * (in.rh[f] + S[f]);
             } else {
@@ -964,8 +964,8 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
 }
 
 // STAGE 1: stage1_cell (Us, R2, rhs unused; Ps = the guess, Uo = U1, Ro = R1)
-// STAGE 2, 3: update_cell
-template <int STAGE, bool CURVED>
+// STAGE 2, 3: update_cell.  HASK: nonzero extrinsic curvature.
+template <int STAGE, bool CURVED, bool HASK>
 __global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const double* __restrict__ sig,
                                                const double* __restrict__ Un, const double* __restrict__ Us,
                                                const double* __restrict__ Ps, const double* __restrict__ R1,
@@ -980,15 +980,15 @@ __global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const 
     long q = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (q >= nchunk) return;                                   // uniform per wave
     StageIn in;
-    stage_load<STAGE, CURVED>(p, q * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, in);
+    stage_load<STAGE, CURVED, HASK>(p, q * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, in);
     for (;;) {
         const long qn = q + W;
         StageIn nx;
         nx.ok = false;
-        if (qn < nchunk) stage_load<STAGE, CURVED>(p, qn * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
+        if (qn < nchunk) stage_load<STAGE, CURVED, HASK>(p, qn * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
         if (in.ok) {
             if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Ps, Po, Ro, Uo, status, nfail);
-            else update_cell<STAGE, CURVED>(p, dt, in, Uo, Po, Ro, status, nfail);
+            else update_cell<STAGE, CURVED, HASK>(p, dt, in, Uo, Po, Ro, status, nfail);
         }
         if (qn >= nchunk) break;
         q = qn;
