@@ -53,9 +53,9 @@ BYTES_PER_CELL = {
     # ghost layers only
     "ghost_fill": 0,
 }
-FLOPS_PER_CELL = {"flux_x": 3257.6, "flux_y": 2790.8, "flux_z": 2792.8, "update_stage2": 2659.4}
-TRAFFIC_BYTES_PER_CELL = {"flux_x": 210.9 + 117.6, "flux_y": 375.5 + 148.1, "flux_z": 377.0 + 155.6,
-                          "update_stage2": 567.5 + 265.4}
+FLOPS_PER_CELL = {"flux_x": 3228.9, "flux_y": 2761.6, "flux_z": 2763.6, "update_stage2": 2495.4}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 184.5 + 116.8, "flux_y": 331.0 + 116.1, "flux_z": 329.9 + 114.8,
+                          "update_stage2": 502.9 + 265.4}
 
 
 def parse():
@@ -69,7 +69,7 @@ def parse():
     ap.add_argument("--full-steps", type=int, default=3, help="timed full IMEX steps (reported beside)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="128,128,96", help="oracle sub-box (nx,ny,nz) for cpu_baseline")
-    ap.add_argument("--cpu-reps", type=int, default=8, help="timed oracle stage-2 applications for cpu_baseline")
+    ap.add_argument("--cpu-reps", type=int, default=12, help="timed oracle stage-2 applications for cpu_baseline")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also launch a plain device copy of known size (for HBM counter calibration)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 stencil) form")
