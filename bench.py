@@ -251,14 +251,19 @@ def main():
         ms = start.elapsed_time(stop)
         kern = g.timing_read()
         g.timing(False)
+        # one more application, untimed, for the recovery iteration histogram
+        g.recovery_stats(True)
+        stage2()
+        hist = g.recovery_stats_read()["stage2"]
+        g.recovery_stats(False)
         nfail = g.failures()
         if nfail:
             raise SystemExit(f"{nfail} failed recoveries in the timed stages")
         del P1, R1, U2, P2, R2
-        return ms, kern
+        return ms, kern, {str(i): c for i, c in enumerate(hist) if c}
 
     evolve(g, U, P, args.evolve, "fp64")
-    ms, kern = time_stage2(g, U, P, args.steps, args.warmup)
+    ms, kern, hist = time_stage2(g, U, P, args.steps, args.warmup)
     value = ncell * args.steps / (ms * 1e-3)
     log(f"stage 2: {ms / args.steps:.3f} ms -> {value:.4g} zone-updates/s")
 
@@ -288,7 +293,7 @@ def main():
     if not args.no_mixed:
         gm, Um, Pm = setup("mixed")
         evolve(gm, Um, Pm, args.evolve, "mixed")
-        ms_m, kern_m = time_stage2(gm, Um, Pm, args.steps, args.warmup)
+        ms_m, kern_m, _ = time_stage2(gm, Um, Pm, args.steps, args.warmup)
         val_m = ncell * args.steps / (ms_m * 1e-3)
         log(f"mixed stage 2: {ms_m / args.steps:.3f} ms -> {val_m:.4g} zone-updates/s")
         # accuracy: both forms from the same seed to the same step count
@@ -360,6 +365,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels_ms_per_launch": per_launch,
+        "stage2_recovery_iterations": hist,
         "full_step": {"ms": ms_step, "zone_updates_per_s_per_stage": 2 * ncell / (ms_step * 1e-3)},
         "mixed": mixed,
         "adjoint": adjoint,

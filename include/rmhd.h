@@ -176,6 +176,18 @@ int rmhd_max_signal_speed(rmhd_ctx* ctx, double* host_out);
  * Synchronises the stream. */
 int rmhd_failures(rmhd_ctx* ctx, int64_t* host_out);
 
+/* Opt-in histograms of recovery iterations (diagnostic, off by default; the
+ * cost of a recovery follows its iteration count, Sec. III.B).  With enable
+ * != 0 the stage kernels count, per recovered cell, the iterations its
+ * recovery took: bins [0, 32) stage 1, [32, 64) stage 2, [64, 96) the final
+ * update, bin b of each = b iterations (the last bin: 31 or more).
+ * rmhd_recovery_stats zeroes the bins when enabling; rmhd_recovery_stats_read
+ * synchronises the stream, writes the 3 * RMHD_HIST_BINS counts and zeroes
+ * them. */
+#define RMHD_HIST_BINS 32
+int rmhd_recovery_stats(rmhd_ctx* ctx, int enable);
+int rmhd_recovery_stats_read(rmhd_ctx* ctx, int64_t* bins_out);
+
 /* Opt-in per-kernel timing (profiling aid, off by default): with enable != 0
  * the library brackets every launch with HIP events on the context's stream,
  * grouped by kernel class: 0 ghost fill, 1 x fluxes, 2 y fluxes, 3 z fluxes,

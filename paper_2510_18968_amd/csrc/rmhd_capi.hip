@@ -21,7 +21,8 @@ struct rmhd_ctx {
     char* ws;
     size_t ws_bytes;
     double *rhs, *P1, *R1, *U2, *P2, *R2;
-    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits, [2] metric scan flag
+    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits, [2] metric scan flag;
+                                    // [32..127] recovery iteration histograms
     bool curved;
     long persist_blocks = 256;   // persistent flux grid: one 4-wave block per CU, multiple of 8
     // opt-in launch timing: event pairs per kernel class, reused after a read
@@ -97,7 +98,7 @@ size_t ws_layout(const rmhd_grid_desc* d, size_t off[7]) {
     off[3] = o; o += f14;   // U2
     off[4] = o; o += f14;   // P2
     off[5] = o; o += f3;    // R2
-    off[6] = o; o += ALIGN; // counters
+    off[6] = o; o += 4 * ALIGN; // counters: 32 words, then the 96 histogram bins
     return o;
 }
 
@@ -571,6 +572,29 @@ int rmhd_failures(rmhd_ctx* c, int64_t* host_out) {
     k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 1);
     LAUNCH_CHECK();
     *host_out = (int64_t)n;
+    return RMHD_OK;
+}
+
+int rmhd_recovery_stats(rmhd_ctx* c, int enable) {
+    if (!c) return fail(RMHD_EINVAL, "null context");
+    if (enable) {
+        k_zero_u64<<<1, 128, 0, c->stream>>>(c->counters + 32, 3 * RMHD_HIST_BINS);
+        LAUNCH_CHECK();
+        c->p.hist = c->counters + 32;
+    } else {
+        c->p.hist = nullptr;
+    }
+    return RMHD_OK;
+}
+
+int rmhd_recovery_stats_read(rmhd_ctx* c, int64_t* bins_out) {
+    if (!c || !bins_out) return fail(RMHD_EINVAL, "null argument");
+    unsigned long long h[3 * RMHD_HIST_BINS];
+    HIP_TRY(hipMemcpyAsync(h, c->counters + 32, sizeof h, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 3 * RMHD_HIST_BINS; ++i) bins_out[i] = (int64_t)h[i];
+    k_zero_u64<<<1, 128, 0, c->stream>>>(c->counters + 32, 3 * RMHD_HIST_BINS);
+    LAUNCH_CHECK();
     return RMHD_OK;
 }
 

@@ -25,6 +25,8 @@ struct Params {
     const double* bet;
     const double* gam;
     const double* K;
+    // opt-in histograms of recovery iterations (3 x RMHD_HIST_BINS), nullptr = off
+    unsigned long long* hist;
 };
 
 __host__ __device__ __forceinline__ bool is_active(const Params& p, int d) { return (p.active >> d) & 1; }
@@ -802,6 +804,21 @@ __device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m,
 // gamma of table imex
 __host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560; }
 
+// recovery iteration histogram: one atomic per distinct count in the wave
+// (called by the active lanes that ran a recovery)
+__device__ __forceinline__ void hist_add(unsigned long long* hist, int it) {
+    const int v = it < 0 ? 0 : (it > 31 ? 31 : it);
+    const int lane = threadIdx.x & 63;
+    unsigned long long todo = __ballot(1);
+    while (todo) {
+        const int leader = __ffsll(todo) - 1;
+        const int val = __shfl(v, leader);
+        const unsigned long long m = __ballot(v == val);
+        if (lane == leader) atomicAdd(hist + val, (unsigned long long)__popcll(m));
+        todo &= ~m;
+    }
+}
+
 // ---------------------------------------------------------- stage kernels
 // Persistent: one wave per SIMD (the recovery's register footprint allows no
 // more) walks 64-cell chunks q, q + W, ...; the loads of the next chunk are
@@ -886,6 +903,7 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
     if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
     else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     __builtin_amdgcn_sched_barrier(0);
+    if (p.hist) hist_add(p.hist, it);                        // stage 1: bins 0..31
     if (st >= 0) {
         write_prims_k(p, o, m, k, in.Un + I_PHI, x, E, P1);
     } else {
@@ -947,6 +965,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
         st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     }
     __builtin_amdgcn_sched_barrier(0);
+    if (p.hist) hist_add(p.hist + (STAGE == 2 ? 32 : 64), it);   // stage 2: 32..63, final: 64..95
     if (st >= 0) {
         write_prims_k(p, o, m, k, cl, x, E, Po);
     } else {

@@ -22,7 +22,8 @@ PREC = {"fp64": 0, "mixed": 1}
 SYMBOLS = ("rmhd_workspace_bytes", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
            "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
-           "rmhd_step_adjoint", "rmhd_prim2con_adjoint")
+           "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read")
+HIST_BINS = 32
 TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
 
 
@@ -71,6 +72,8 @@ def lib() -> C.CDLL:
             "rmhd_adjoint_workspace_bytes": (C.c_size_t, [gp]),
             "rmhd_step_adjoint": (C.c_int, [vp, C.c_double, vp, vp, vp, vp, vp, vp, vp, C.c_size_t]),
             "rmhd_prim2con_adjoint": (C.c_int, [vp, vp, vp, vp]),
+            "rmhd_recovery_stats": (C.c_int, [vp, C.c_int]),
+            "rmhd_recovery_stats_read": (C.c_int, [vp, C.POINTER(C.c_int64)]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -214,6 +217,17 @@ class Grid:
         _check(lib().rmhd_prim2con_adjoint(self._ctx, self._ptr(P, 14), self._ptr(Ubar, 14), self._ptr(Pbar, 14)),
                "rmhd_prim2con_adjoint")
         return Pbar
+
+    def recovery_stats(self, enable=True):
+        _check(lib().rmhd_recovery_stats(self._ctx, 1 if enable else 0), "rmhd_recovery_stats")
+
+    def recovery_stats_read(self):
+        """{"stage1": counts, "stage2": counts, "final": counts}, counts[b] =
+        cells whose recovery took b iterations (last bin: 31 or more)"""
+        a = (C.c_int64 * (3 * HIST_BINS))()
+        _check(lib().rmhd_recovery_stats_read(self._ctx, a), "rmhd_recovery_stats_read")
+        v = list(a)
+        return {"stage1": v[:HIST_BINS], "stage2": v[HIST_BINS:2 * HIST_BINS], "final": v[2 * HIST_BINS:]}
 
     def timing(self, enable=True):
         _check(lib().rmhd_timing(self._ctx, 1 if enable else 0), "rmhd_timing")
