@@ -124,9 +124,31 @@ template <class R, class T> __device__ __forceinline__ R after(R v, T dep) {
     return v;
 }
 
+// Whole-wave lane shifts by DPP (VALU moves, no LDS round trip):
+// up<N>(v) on lane i is v of lane i - N, down<N>(v) is v of lane i + N; lanes
+// whose source is off the wave keep their own v (they carry no used result).
+// Every lane of the wave must be active.
+__device__ __forceinline__ int dpp_up1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
+__device__ __forceinline__ int dpp_dn1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+// (FP32 keeps the LDS-routed shuffle: a single DPP move per value leaves the
+// dependent shifts of a stencil back to back, which measured slower)
+template <bool UP> __device__ __forceinline__ float shift1(float v) { return UP ? __shfl_up(v, 1) : __shfl_down(v, 1); }
+template <bool UP> __device__ __forceinline__ double shift1(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    return __hiloint2double(UP ? dpp_up1(hi) : dpp_dn1(hi), UP ? dpp_up1(lo) : dpp_dn1(lo));
+}
+template <int N, class R> __device__ __forceinline__ R up(R v) {
+    for (int k = 0; k < N; ++k) v = shift1<true>(v);
+    return v;
+}
+template <int N, class R> __device__ __forceinline__ R down(R v) {
+    for (int k = 0; k < N; ++k) v = shift1<false>(v);
+    return v;
+}
+
 template <class R> __device__ __forceinline__ R face4(R a) {
     // value at the face between this lane's cell and the next one, 4th order
-    const R am = __shfl_up(a, 1), ap = __shfl_down(a, 1), app = __shfl_down(a, 2);
+    const R am = up<1>(a), ap = down<1>(a), app = down<2>(a);
     return (-am + 9.0 * a + 9.0 * ap - app) * 0.0625;
 }
 
@@ -217,14 +239,15 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
         current(mc, in.P, in.s, J);
         JD = J[D];
     }
-    const R Jf = R(0.5 * (JD + __shfl_down(JD, 1)));
+    const R Jf = R(0.5 * (JD + down<1>(JD)));
     __builtin_amdgcn_sched_barrier(0);
     R fm[NF], fp[NF];
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         // two fields in flight: the shuffles of f wait for field f - 2
         const R v = f >= 2 ? after(R(in.P[f]), fp[f - 2]) : R(in.P[f]);
-        const R st[5] = {__shfl_up(v, 2), __shfl_up(v, 1), v, __shfl_down(v, 1), __shfl_down(v, 2)};
+        const R v1 = up<1>(v), w1 = down<1>(v);
+        const R st[5] = {up<1>(v1), v1, v, w1, down<1>(w1)};
         recon<RECON>(st, fm[f], fp[f]);
     }
     // face between this lane's cell and the next
@@ -240,7 +263,7 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
     }
     R PR[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) PR[f] = __shfl_down(fm[f], 1);
+    for (int f = 0; f < NF; ++f) PR[f] = down<1>(fm[f]);
     __builtin_amdgcn_sched_barrier(0);
     // first-order fallback; only faces whose right cell lies inside the padded
     // range (the clamped edge lanes carry no face that is used)
@@ -257,7 +280,7 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
         // differences from the neighbouring lanes
         const double cd = p.idx[D] / 12.0;
         auto dD = [&](double f) {
-            const double m2 = __shfl_up(f, 2), m1 = __shfl_up(f, 1), p1 = __shfl_down(f, 1), p2 = __shfl_down(f, 2);
+            const double m1 = up<1>(f), p1 = down<1>(f), m2 = up<1>(m1), p2 = down<1>(p1);
             return (m2 - 8.0 * m1 + 8.0 * p1 - p2) * cd;
         };
         double dg[6], db[3] = {0.0, 0.0, 0.0};
@@ -272,7 +295,7 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
     const R ih = R(p.idx[D]);
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
-        const R Fl = __shfl_up(Fh[f], 1);
+        const R Fl = up<1>(Fh[f]);
         if (cell) rhs[f * Np + o] = acc[f] + double(-(Fh[f] - Fl) * ih);
     }
 }

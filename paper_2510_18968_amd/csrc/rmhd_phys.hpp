@@ -425,20 +425,23 @@ enum : int { ST_OK = 0, ST_WARN = 1, ST_NOCONV = -3, ST_UNPHYS = -4 };
 
 // exact Jacobian of the recovery map at x, one dual direction per column,
 // factorised in place; r = residual at x
-__device__ __forceinline__ bool rec_jacobian(const RecIn& k, const double* x, double J[4][4], int* piv, double* r) {
+// residual r and LU of its Jacobian at x: 0, or JAC_UNPHYS (x outside the
+// physical domain), or JAC_SINGULAR
+enum { JAC_OK = 0, JAC_UNPHYS = 1, JAC_SINGULAR = 2 };
+__device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, double J[4][4], int* piv, double* r) {
 #pragma unroll 1
     for (int b = 0; b < 4; ++b) {
         D1 xd[4], rd[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) xd[a] = D1{x[a], a == b ? 1.0 : 0.0};
-        if (!rec_residual<D1>(k, xd, rd, (D1*)nullptr)) return false;
+        if (!rec_residual<D1>(k, xd, rd, (D1*)nullptr)) return JAC_UNPHYS;
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
             r[a] = rd[a].v;
             J[a][b] = rd[a].d;
         }
     }
-    return lu4(J, piv);
+    return lu4(J, piv) ? JAC_OK : JAC_SINGULAR;
 }
 
 // Stiff coupled solve: the root of the recovery map r(p, v) (the fixed point
@@ -450,8 +453,12 @@ __device__ __forceinline__ bool rec_jacobian(const RecIn& k, const double* x, do
 __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, int maxit, int* iters) {
     double r[4];
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
-    if (!rec_residual<double>(k, x, r, (double*)nullptr)) {
-        // outside the physical domain: restart at rest with a larger pressure
+    double J[4][4];
+    int piv[4];
+    // the Jacobian passes also give the residual at the guess
+    int jst = rec_jacobian(k, x, J, piv, r);
+    if (jst == JAC_UNPHYS) {
+        // guess outside the physical domain: restart at rest with a larger pressure
         x[1] = x[2] = x[3] = 0.0;
         bool ok = false;
         for (int i = 0; i < 64 && !ok; ++i) {
@@ -459,10 +466,9 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
             if (!ok) x[0] *= 2.0;
         }
         if (!ok) { *iters = 0; return ST_UNPHYS; }
+        jst = rec_jacobian(k, x, J, piv, r);
     }
-    double J[4][4];
-    int piv[4];
-    if (!rec_jacobian(k, x, J, piv, r)) { *iters = 0; return ST_NOCONV; }
+    if (jst != JAC_OK) { *iters = 0; return ST_NOCONV; }
     bool fresh = true;
     double last_rel = 1e300, prev_step = 1e300;
     for (int it = 1; it <= maxit; ++it) {
@@ -483,7 +489,7 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
         }
         if (!acc) {
             if (fresh) { *iters = it; return ST_NOCONV; }
-            if (!rec_jacobian(k, x, J, piv, r)) { *iters = it; return ST_NOCONV; }
+            if (rec_jacobian(k, x, J, piv, r) != JAC_OK) { *iters = it; return ST_NOCONV; }
             fresh = true;
             continue;
         }
@@ -495,7 +501,7 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
         if (dp <= tol * x[0] && dv <= tol) { *iters = it; return ST_OK; }
         const double step = fmax(last_rel, dv);
         if (t < 1.0 || step > 0.25 * prev_step) {
-            if (!rec_jacobian(k, x, J, piv, r)) { *iters = it; return ST_NOCONV; }
+            if (rec_jacobian(k, x, J, piv, r) != JAC_OK) { *iters = it; return ST_NOCONV; }
             fresh = true;
         } else {
             fresh = false;
