@@ -140,19 +140,18 @@ __global__ __launch_bounds__(128) void k_adj_face(const Params p, const double* 
     speeds<D>(p, m, lp, lm);
     const double id = frcp(lp - lm);
     const double cL = lp * id, cR = -lm * id, cU = lp * lm * id;
-    // J enters only the charge flux, F_Q = alpha J - beta Q on both sides
-    const double Jd = 0.0;
+    // Fh = cL F(PL) - cU U(PL) + cR F(PR) + cU U(PR); the face current enters
+    // only the charge flux (F_Q = alpha J - beta Q), its adjoint is fb[28]
     for (int side = 0; side < 2; ++side) {
         const double* Ps = side ? PR : PL;
         const double cF = side ? cR : cL, cS = side ? cU : -cU;
-        for (int a = 0; a < NF; ++a) {
-            D1 Pd[NF], Ud[NF], Fd[NF];
-            for (int f = 0; f < NF; ++f) Pd[f] = D1(Ps[f], f == a ? 1.0 : 0.0);
-            state_flux<D>(m, D1(p.G), Pd, D1(Jd), Ud, Fd);
-            double acc = 0.0;
-            for (int f = 0; f < NF; ++f) acc += Fb[f] * (cF * Fd[f].d + cS * Ud[f].d);
-            fb[(side * NF + a) * Np + o] = acc;
+        double wF[NF], wU[NF], Pb[NF];
+        for (int f = 0; f < NF; ++f) {
+            wF[f] = Fb[f] * cF;
+            wU[f] = Fb[f] * cS;
         }
+        state_flux_vjp<D>(m, p.G, Ps, wF, wU, Pb);
+        for (int a = 0; a < NF; ++a) fb[(side * NF + a) * Np + o] = Pb[a];
     }
     fb[28 * Np + o] = m.alp * Fb[I_Q];
     fb[29 * Np + o] = (double)flags;
@@ -247,8 +246,9 @@ __global__ __launch_bounds__(128) void k_adj_cell(const Params p, const double* 
 
 // --------------------------------------------------- ghost fill (reverse)
 // the ghost cells along d are copies of interior cells: add their adjoints to
-// the images and clear them (one thread owns one image row, deterministic)
-__global__ void k_adj_fold(const Params p, double* __restrict__ a, int nf, int d) {
+// the images and clear them (one thread owns one image row, deterministic);
+// the nf fields of a and then the one field of b
+__global__ void k_adj_fold(const Params p, double* __restrict__ a, int nf, double* __restrict__ b1, int d) {
     const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
     const long n1 = p.n[e1], n2 = p.n[e2];
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -258,8 +258,8 @@ __global__ void k_adj_fold(const Params p, double* __restrict__ a, int nf, int d
     const long a1 = t % n1 + p.g[e1], a2 = t / n1 + p.g[e2];
     const long ob = a1 * p.st[e1] + a2 * p.st[e2];
     const int g = p.g[d], n = p.n[d];
-    for (int f = 0; f < nf; ++f) {
-        double* b = a + f * p.Np + ob;
+    for (int f = 0; f <= nf; ++f) {
+        double* b = (f < nf ? a + f * p.Np : b1) + ob;
         for (int l = 0; l < g; ++l) {
             const int c = side ? n + g + l : l;
             const int src = bc_map(p, d, c);

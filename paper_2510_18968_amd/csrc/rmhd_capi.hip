@@ -292,9 +292,7 @@ template <bool CURVED, int RECON> int adj_L_t(rmhd_ctx* c, const double* P, cons
         if (!is_active(p, d)) continue;
         const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
         const long nt = 2L * p.n[e1] * p.n[e2];
-        k_adj_fold<<<nblk(nt, 256), 256, 0, c->stream>>>(p, Pb, NF, d);
-        LAUNCH_CHECK();
-        k_adj_fold<<<nblk(nt, 256), 256, 0, c->stream>>>(p, sb, 1, d);
+        k_adj_fold<<<nblk(nt, 256), 256, 0, c->stream>>>(p, Pb, NF, sb, d);
         LAUNCH_CHECK();
     }
     return RMHD_OK;

@@ -176,6 +176,128 @@ __device__ __forceinline__ void state_flux(const Geo<M>& m, R G, const R* P, R J
     F[I_Q] = a * Jd - bd * U[I_Q];
 }
 
+// Reverse of state_flux at one state (the face current Jd held fixed):
+// Pb = (dF/dP)^T wF + (dU/dP)^T wU, by the chain rule through the same
+// intermediates (lowered vectors, W, h, E x B) in reverse order.
+template <int D>
+__device__ __forceinline__ void state_flux_vjp(const Geo<double>& m, double G, const double* P, const double* wF,
+                                               const double* wU, double* Pb) {
+    const double* v = P + I_V;
+    const double* B = P + I_B;
+    const double* E = P + I_E;
+    double vl[3], Bl[3], El[3], c[3];
+    lower(m.g, v, vl);
+    lower(m.g, B, Bl);
+    lower(m.g, E, El);
+    const double W = frsqrt(1.0 - dot3(vl, v));
+    const double kap = G / (G - 1.0);
+    const double h = P[I_RHO] + kap * P[I_P];
+    const double hW2 = h * (W * W);
+    cross(E, B, c);
+    const double sg = m.sg, a = m.alp, bd = m.bet[D], as = m.alp * sg;
+    const double Dd = P[I_RHO] * W * sg;
+    const double vd = v[D], Ed = E[D], Bd = B[D];
+    // adjoints of U (direct weights and through F's -beta U terms) and of the intermediates
+    double Ub[NF];
+    for (int f = 0; f < NF; ++f) Ub[f] = wU[f] - bd * wF[f];
+    double vd_b = 0.0, Dd_b = 0.0, hW2_b = 0.0, Ed_b = 0.0, Bd_b = 0.0, pt_b = 0.0, em_b = 0.0;
+    double vl_b[3] = {0.0, 0.0, 0.0}, El_b[3] = {0.0, 0.0, 0.0}, Bl_b[3] = {0.0, 0.0, 0.0};
+    // F_D = a vd Dd - bd U_D (the second term is in Ub)
+    vd_b += wF[I_D] * a * Dd;
+    Dd_b += wF[I_D] * a * vd;
+    // F_S_i = as (hW2 vd vl_i - Ed El_i - Bd Bl_i + delta_iD pt) - bd U_S_i
+    for (int i = 0; i < 3; ++i) {
+        const double w = wF[I_S + i] * as;
+        hW2_b += w * vd * vl[i];
+        vd_b += w * hW2 * vl[i];
+        vl_b[i] += w * hW2 * vd;
+        Ed_b -= w * El[i];
+        El_b[i] -= w * Ed;
+        Bd_b -= w * Bl[i];
+        Bl_b[i] -= w * Bd;
+    }
+    pt_b += wF[I_S + D] * as;
+    // F_tau = a (Sd - vd Dd) - bd U_tau, Sd = U_S_i gamma^{Di}
+    {
+        const double w = wF[I_TAU] * a;
+        for (int i = 0; i < 3; ++i) Ub[I_S + i] += w * m.gi[sidx(D, i)];
+        vd_b -= w * Dd;
+        Dd_b -= w * vd;
+    }
+    // F_B_i = a ((e_D x E_l)_i + gamma^{iD} U_phi) - bd U_B_i, F_E_i = -a ((e_D x B_l)_i - gamma^{iD} U_psi) - bd U_E_i
+    // with (e_D x X)_i = X_{D+2} for i = D+1 and -X_{D+1} for i = D+2 (indices mod 3)
+    {
+        const int i1 = (D + 1) % 3, i2 = (D + 2) % 3;
+        El_b[i2] += -a * wF[I_B + i1];
+        El_b[i1] += a * wF[I_B + i2];
+        Bl_b[i2] -= -a * wF[I_E + i1];
+        Bl_b[i1] -= a * wF[I_E + i2];
+        for (int i = 0; i < 3; ++i) {
+            Ub[I_PHI] += a * wF[I_B + i] * m.gi[sidx(i, D)];
+            Ub[I_PSI] += a * wF[I_E + i] * m.gi[sidx(i, D)];
+        }
+        Ub[I_B + D] += a * wF[I_PHI];
+        Ub[I_E + D] += a * wF[I_PSI];
+    }
+    // U -> intermediates
+    Dd_b += Ub[I_D];
+    double c_b[3];
+    for (int i = 0; i < 3; ++i) {
+        hW2_b += Ub[I_S + i] * sg * vl[i];
+        vl_b[i] += Ub[I_S + i] * sg * hW2;
+        c_b[i] = Ub[I_S + i] * sg * sg;
+    }
+    double p_b = 0.0;
+    hW2_b += Ub[I_TAU] * sg;
+    p_b -= Ub[I_TAU] * sg;
+    em_b += Ub[I_TAU] * sg;
+    Dd_b -= Ub[I_TAU];
+    // pt = p + em
+    p_b += pt_b;
+    em_b += pt_b;
+    double v_b[3], B_b[3], E_b[3];
+    for (int i = 0; i < 3; ++i) {
+        B_b[i] = Ub[I_B + i] * sg + em_b * Bl[i];
+        E_b[i] = Ub[I_E + i] * sg + em_b * El[i];
+    }
+    // c = E x B: E_b += B x c_b, B_b += c_b x E
+    E_b[0] += B[1] * c_b[2] - B[2] * c_b[1];
+    E_b[1] += B[2] * c_b[0] - B[0] * c_b[2];
+    E_b[2] += B[0] * c_b[1] - B[1] * c_b[0];
+    B_b[0] += c_b[1] * E[2] - c_b[2] * E[1];
+    B_b[1] += c_b[2] * E[0] - c_b[0] * E[2];
+    B_b[2] += c_b[0] * E[1] - c_b[1] * E[0];
+    E_b[D] += Ed_b;
+    B_b[D] += Bd_b;
+    // El = g E, Bl = g B (g symmetric)
+    double t[3];
+    lower(m.g, El_b, t);
+    for (int i = 0; i < 3; ++i) E_b[i] += t[i];
+    lower(m.g, Bl_b, t);
+    for (int i = 0; i < 3; ++i) B_b[i] += t[i];
+    // Dd = rho W sg, hW2 = h W^2, h = rho + kap p
+    double rho_b = Dd_b * W * sg;
+    double W_b = Dd_b * P[I_RHO] * sg + hW2_b * 2.0 * h * W;
+    const double h_b = hW2_b * W * W;
+    rho_b += h_b;
+    p_b += kap * h_b;
+    // W = (1 - vl.v)^(-1/2): dW/d(vl.v) = W^3 / 2; d(vl.v)/dv = 2 vl
+    const double v2_b = W_b * 0.5 * W * W * W;
+    lower(m.g, vl_b, t);
+    for (int i = 0; i < 3; ++i) v_b[i] = 2.0 * v2_b * vl[i] + t[i];
+    v_b[D] += vd_b;
+    Pb[I_RHO] = rho_b;
+    Pb[I_P] = p_b;
+    for (int i = 0; i < 3; ++i) {
+        Pb[I_V + i] = v_b[i];
+        Pb[I_B + i] = B_b[i];
+        Pb[I_E + i] = E_b[i];
+    }
+    Pb[I_PHI] = Ub[I_PHI] * sg;
+    Pb[I_PSI] = Ub[I_PSI] * sg;
+    Pb[I_Q] = Ub[I_Q] * sg;
+}
+
 // ---------------------------------------------------------------- reconstruction
 template <class R> __device__ __forceinline__ R mm2(R a, R b) {
     // minmod: 0 unless a, b share a sign, else the one of smaller magnitude
