@@ -265,13 +265,16 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
 #pragma unroll
     for (int f = 0; f < NF; ++f) PR[f] = down<1>(fm[f]);
     __builtin_amdgcn_sched_barrier(0);
-    // first-order fallback; only faces whose right cell lies inside the padded
-    // range (the clamped edge lanes carry no face that is used)
-    const bool face = it.cp + 1 < nD + 2 * gD;
-    if (face && bad_state(m, fp))
+    // first-order fallback: the cell values of this lane and of the next one
+    // (taken from the neighbouring lane, not reloaded: a load here would make
+    // every later wait also wait for the next segment's prefetch)
+    R Pn[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) Pn[f] = R(down<1>(in.P[f]));
+    if (bad_state(m, fp))
         for (int f = 0; f < NF; ++f) fp[f] = R(in.P[f]);
-    if (face && bad_state(m, PR))
-        for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + o + s]);
+    if (bad_state(m, PR))
+        for (int f = 0; f < NF; ++f) PR[f] = Pn[f];
     R Fh[NF];
     face_flux<D>(p, m, fp, PR, Jf, Fh);
 
@@ -329,12 +332,12 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
     flux_load<D, CURVED>(p, P, sig, it, in);
     for (;;) {
         const long nxt = wid + W;
-        FluxItem<D> it2 = it;
+        // unconditional (the last pass reloads a valid item): a branch around
+        // the loads leaves the wait-count pass unsure of what is in flight and
+        // it then waits for the prefetch right after issuing it
+        const FluxItem<D> it2 = flux_item<D>(p, nxt < nitems ? nxt : wid, nseg, lane);
         FluxIn in2;
-        if (nxt < nitems) {
-            it2 = flux_item<D>(p, nxt, nseg, lane);
-            flux_load<D, CURVED>(p, P, sig, it2, in2);
-        }
+        flux_load<D, CURVED>(p, P, sig, it2, in2);
         flux_compute<D, RECON, CURVED, R, ACC>(p, P, rhs, it, in, lane);
         if (nxt >= nitems) break;
         wid = nxt;
@@ -511,13 +514,14 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             } else {
                 geo_flat(m);
             }
+            // first-order fallback from the ring (rows c-1 and c are not the slot in flight)
             if (bad_state(m, PLc))
-                for (int f = 0; f < NF; ++f) PLc[f] = R(P[f * Np + base + (long)(c - 1 + gD) * s]);
+                for (int f = 0; f < NF; ++f) PLc[f] = R(ringP(c - 1, f));
             R PR[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) PR[f] = fm[f];
             if (bad_state(m, PR))
-                for (int f = 0; f < NF; ++f) PR[f] = R(P[f * Np + base + (long)(c + gD) * s]);
+                for (int f = 0; f < NF; ++f) PR[f] = R(ringP(c, f));
             R Fh[NF];
             face_flux<D>(p, m, PLc, PR, R(0.5 * (Jprev + Jc)), Fh);
             if (fin && valid) {
@@ -859,8 +863,11 @@ __device__ __forceinline__ void stage_load(const Params& p, long t, const double
                                            const double* __restrict__ Un, const double* __restrict__ Us,
                                            const double* __restrict__ Ps, const double* __restrict__ R1,
                                            const double* __restrict__ R2, const double* __restrict__ rhs, StageIn& in) {
-    in.ok = interior_cell(p, t, in.o);
-    if (!in.ok) return;
+    // branch-free: a lane past the last cell loads the last cell (ok = false),
+    // so that the wait-count pass sees the same loads in flight on every path
+    const long ncell = (long)p.n[0] * p.n[1] * p.n[2];
+    in.ok = t < ncell;
+    interior_cell(p, in.ok ? t : ncell - 1, in.o);
     const long Np = p.Np, o = in.o;
 #pragma unroll
     for (int f = 0; f < NF; ++f) in.Un[f] = Un[f * Np + o];
@@ -1025,9 +1032,9 @@ __global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const 
     stage_load<STAGE, CURVED, HASK>(p, q * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, in);
     for (;;) {
         const long qn = q + W;
+        // unconditional (the last pass reloads its own chunk)
         StageIn nx;
-        nx.ok = false;
-        if (qn < nchunk) stage_load<STAGE, CURVED, HASK>(p, qn * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
+        stage_load<STAGE, CURVED, HASK>(p, (qn < nchunk ? qn : q) * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
         if (in.ok) {
             if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Ps, Po, Ro, Uo, status, nfail);
             else update_cell<STAGE, CURVED, HASK>(p, dt, in, Uo, Po, Ro, status, nfail);
