@@ -75,6 +75,7 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 stencil) form")
     ap.add_argument("--mixed-steps", type=int, default=50, help="steps of the FP64-vs-mixed accuracy run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint rollout timing")
+    ap.add_argument("--no-other-recon", action="store_true", help="skip timing the other reconstruction (MC2/WENO5)")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="steps of the differentiated rollout")
     return ap.parse_args()
 
@@ -203,8 +204,8 @@ def main():
     sig = torch.from_numpy(w.sigma).cuda()
     ncell = w.n_interior
 
-    def setup(precision):
-        g = rmhd.grid_for(w, precision=precision)
+    def setup(precision, recon=None):
+        g = rmhd.grid_for(w, precision=precision, **({"recon": recon} if recon else {}))
         g.set_metric(met)
         P = torch.from_numpy(w.P).cuda()
         U = g.prim2con(P)
@@ -289,6 +290,18 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    # the other reconstruction of the same workload, on the same evolved state
+    other = None
+    if not args.no_other_recon:
+        orec = "mc2" if args.recon == "weno5" else "weno5"
+        go, _, _ = setup("fp64", orec)
+        ms_o, kern_o, _ = time_stage2(go, U, P, args.steps, args.warmup)
+        other = {"recon": orec, "value": ncell * args.steps / (ms_o * 1e-3), "unit": "zone-updates/s",
+                 "ms_per_step": ms_o / args.steps,
+                 "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern_o.items()}}
+        log(f"{orec} stage 2 on the same state: {ms_o / args.steps:.3f} ms")
+        del go
+
     mixed = None
     if not args.no_mixed:
         gm, Um, Pm = setup("mixed")
@@ -367,6 +380,7 @@ def main():
         "kernels_ms_per_launch": per_launch,
         "stage2_recovery_iterations": hist,
         "full_step": {"ms": ms_step, "zone_updates_per_s_per_stage": 2 * ncell / (ms_step * 1e-3)},
+        "other_recon": other,
         "mixed": mixed,
         "adjoint": adjoint,
     }
