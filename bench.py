@@ -53,9 +53,9 @@ BYTES_PER_CELL = {
     # ghost layers only
     "ghost_fill": 0,
 }
-FLOPS_PER_CELL = {"flux_x": 3228.9, "flux_y": 2761.6, "flux_z": 2763.6, "update_stage2": 2495.4}
-TRAFFIC_BYTES_PER_CELL = {"flux_x": 184.5 + 116.8, "flux_y": 331.0 + 116.1, "flux_z": 329.9 + 114.8,
-                          "update_stage2": 502.9 + 265.4}
+FLOPS_PER_CELL = {"flux_x": 3228.9, "flux_y": 2761.6, "flux_z": 2763.6, "update_stage2": 2318.3}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 185.1 + 116.6, "flux_y": 331.5 + 116.3, "flux_z": 329.9 + 115.0,
+                          "update_stage2": 508.2 + 265.0}
 
 
 def parse():
