@@ -48,8 +48,10 @@ BYTES_PER_CELL = {
     # as x, plus the read half of the rhs read-modify-write
     "flux_y": 8 * (14 + 1 + 7 + 14 + 14),
     "flux_z": 8 * (14 + 1 + 7 + 14 + 14),
-    # P(1) 14, U^n 14, rhs 14, R1 3, sigma 1, metric 7 read; U(2) 14, P(2) 14, R2 3 written
-    "update_stage2": 8 * (14 + 14 + 14 + 3 + 1 + 7 + 14 + 14 + 3),
+    # P(1) 7 (p, v and the cleaning fields: the guess and, without K, all the
+    # local sources read), U^n 14, rhs 14, R1 3, sigma 1, metric 7 read;
+    # U(2) 14, P(2) 14, R2 3 written
+    "update_stage2": 8 * (7 + 14 + 14 + 3 + 1 + 7 + 14 + 14 + 3),
     # ghost layers only
     "ghost_fill": 0,
 }
@@ -200,14 +202,18 @@ def main():
     t0 = time.perf_counter()
     w = W.curved_blob(n=args.n, recon=args.recon)
     log(f"inputs generated in {time.perf_counter() - t0:.1f} s: {w.name}, padded {w.padded}")
-    met = torch.from_numpy(w.metric).cuda()
-    sig = torch.from_numpy(w.sigma).cuda()
     ncell = w.n_interior
+    # interior x rows on 128-byte lines (16 cells of x padding)
+    met = sig = None
 
     def setup(precision, recon=None):
-        g = rmhd.grid_for(w, precision=precision, **({"recon": recon} if recon else {}))
+        nonlocal met, sig
+        g = rmhd.grid_for(w, precision=precision, x_align=1, **({"recon": recon} if recon else {}))
+        if met is None:
+            met = g.to_layout(w.metric)
+            sig = g.to_layout(w.sigma)
         g.set_metric(met)
-        P = torch.from_numpy(w.P).cuda()
+        P = g.to_layout(w.P)
         U = g.prim2con(P)
         return g, U, P
 
@@ -314,6 +320,7 @@ def main():
         evolve(g, U, P, rest, "fp64 accuracy run")
         evolve(gm, Um, Pm, rest, "mixed accuracy run")
         I = (slice(None),) + tuple(w.interior)
+        P, Pm = g.from_layout(P), gm.from_layout(Pm)     # the 3-ghost layout of w.interior
         names = ["rho", "p", "vx", "vy", "vz", "Bx", "By", "Bz", "Ex", "Ey", "Ez", "phi", "psi", "q"]
         errs = {}
         # E (slaved to -v x B in the stiff interior) is measured against the

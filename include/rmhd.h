@@ -18,8 +18,14 @@
  *    workspace, so the library never allocates device memory itself.
  *  - Layout: float64, structure of arrays, field-major
  *    a[f][k][j][i] with i (x) fastest, over the PADDED grid: along every
- *    active dimension d there are ng = 3 ghost cells on each side, inactive
- *    dimensions carry none.  Np = prod_d (n[d] + 2 ghost_d).
+ *    active dimension d there are pad_d cells on each side of the interior,
+ *    inactive dimensions carry none.  pad_d = ng = 3, except along x with
+ *    x_align = 1, where pad_x = 16: the 3 cells next to the interior are the
+ *    ghost cells, the other 13 are never read or written.  With n[0] a
+ *    multiple of 16 and a 128-byte aligned base pointer every interior x row
+ *    then starts on a 128-byte line, which the streaming kernels read and
+ *    write as whole lines.  Np = prod_d (n[d] + 2 pad_d);
+ *    rmhd_padded_extent() returns the three extents.
  *  - Primitive vector P (14): rho, p, v^x, v^y, v^z, B^x, B^y, B^z,
  *    E^x, E^y, E^z, phi, psi, q (contravariant, not densitised; v is the
  *    Eulerian 3-velocity of Sec. II.A).
@@ -78,6 +84,8 @@ typedef struct {
     int32_t c2p_maxit;   /* recovery iteration cap (default 500)               */
     int32_t speed_mode;  /* 0: +-sqrt(gamma^dd) - beta^d/alpha as printed in
                             Sec. III; 1: alpha sqrt(gamma^dd) -+ beta^d        */
+    int32_t x_align;     /* 0: 3 cells of padding along x, as along y and z;
+                            1: 16 (aligned interior rows, see Layout)          */
     double x0[3];        /* centre of the first interior cell                  */
     double dx[3];        /* cell widths                                        */
     double gamma_ad;     /* ideal-gas adiabatic index Gamma (Sec. III.B)        */
@@ -112,6 +120,11 @@ typedef struct {
 /* Bytes of device workspace a context needs for this grid (>= 0; 0 on an
  * invalid descriptor, see rmhd_last_error). */
 size_t rmhd_workspace_bytes(const rmhd_grid_desc* desc);
+
+/* Padded extents {x, y, z} of the arrays of this grid (see Layout) into
+ * host_out[3]; host only, no device work.  RMHD_EINVAL on an invalid
+ * descriptor or a NULL host_out. */
+int rmhd_padded_extent(const rmhd_grid_desc* desc, int32_t* host_out);
 
 /* Create a context.  workspace: device memory of at least
  * rmhd_workspace_bytes(desc) bytes, 256-byte aligned, owned by the caller and

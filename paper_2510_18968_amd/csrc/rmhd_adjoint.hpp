@@ -260,8 +260,8 @@ __global__ void k_adj_fold(const Params p, double* __restrict__ a, int nf, doubl
     const int g = p.g[d], n = p.n[d];
     for (int f = 0; f <= nf; ++f) {
         double* b = (f < nf ? a + f * p.Np : b1) + ob;
-        for (int l = 0; l < g; ++l) {
-            const int c = side ? n + g + l : l;
+        for (int l = 0; l < p.ng; ++l) {
+            const int c = side ? n + g + l : g - p.ng + l;
             const int src = bc_map(p, d, c);
             const double v = b[(long)c * p.st[d]];
             b[(long)c * p.st[d]] = 0.0;
@@ -282,6 +282,7 @@ __device__ __forceinline__ bool stage_omega(const Params& p, const Geo<double>& 
     RecInT<S> k;
     k.G = p.G;
     k.D = th[0];
+    k.iD = inv(k.D);
     k.S[0] = th[1]; k.S[1] = th[2]; k.S[2] = th[3];
     k.tau = th[4];
     for (int i = 0; i < 3; ++i) {

@@ -55,6 +55,14 @@ int fail(int code, const std::string& msg) {
 constexpr size_t ALIGN = 256;
 size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
 
+// padding on each side of dimension k: the ghost width on active dimensions,
+// X_ALIGN_PAD along an active x with x_align (interior rows on 128-byte lines)
+constexpr int X_ALIGN_PAD = 16;
+int pad_lo(const rmhd_grid_desc* d, int k) {
+    if (!((d->active_mask >> k) & 1)) return 0;
+    return (k == 0 && d->x_align) ? X_ALIGN_PAD : d->ng;
+}
+
 bool check_desc(const rmhd_grid_desc* d, std::string& why) {
     if (!d) { why = "null descriptor"; return false; }
     if (d->ng != 3) { why = "ng must be 3"; return false; }
@@ -76,15 +84,16 @@ bool check_desc(const rmhd_grid_desc* d, std::string& why) {
     if (!(d->kappa >= 0.0)) { why = "kappa must be >= 0"; return false; }
     if (!(d->c2p_tol > 0.0) || d->c2p_maxit < 1) { why = "bad recovery tolerance or cap"; return false; }
     if (d->speed_mode != 0 && d->speed_mode != 1) { why = "bad speed_mode"; return false; }
+    if (d->x_align != 0 && d->x_align != 1) { why = "x_align must be 0 or 1"; return false; }
     long np = 1;
-    for (int k = 0; k < 3; ++k) np *= d->n[k] + (((d->active_mask >> k) & 1) ? 2 * d->ng : 0);
+    for (int k = 0; k < 3; ++k) np *= d->n[k] + 2 * pad_lo(d, k);
     if (np > (1L << 36)) { why = "grid too large"; return false; }
     return true;
 }
 
 long padded_cells(const rmhd_grid_desc* d) {
     long np = 1;
-    for (int k = 0; k < 3; ++k) np *= d->n[k] + (((d->active_mask >> k) & 1) ? 2 * d->ng : 0);
+    for (int k = 0; k < 3; ++k) np *= d->n[k] + 2 * pad_lo(d, k);
     return np;
 }
 
@@ -134,7 +143,7 @@ int ghost_fill(rmhd_ctx* c, double* a, int nf) {
     for (int d = 0; d < 3; ++d) {
         if (!is_active(p, d)) continue;
         const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
-        const long tot = 2L * p.g[d] * p.n[e1] * p.n[e2];
+        const long tot = 2L * p.ng * p.n[e1] * p.n[e2];
         Timed t(c, T_GHOST);
         k_ghost<<<nblk(tot, 256), 256, 0, c->stream>>>(p, a, nf, d);
         LAUNCH_CHECK();
@@ -217,7 +226,8 @@ template <int STAGE>
 int launch_stage(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Us, const double* Ps,
                  const double* R1, const double* R2, double* Uo, double* Po, double* Ro, int32_t* st) {
     const long nchunk = (ncells(c->p) + 63) / 64;
-    const long blocks = std::max<long>(1, std::min<long>(c->persist_blocks, (nchunk + 3) / 4));
+    // a multiple of 8, so that the XCD renumbering of the blocks is a bijection
+    const long blocks = std::min<long>(c->persist_blocks, ((nchunk + 3) / 4 + 7) / 8 * 8);
     if (c->curved && c->p.K)
         k_stage<STAGE, true, true><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
                                                                    Ro, st, c->counters);
@@ -407,6 +417,14 @@ size_t rmhd_workspace_bytes(const rmhd_grid_desc* desc) {
     return ws_layout(desc, off);
 }
 
+int rmhd_padded_extent(const rmhd_grid_desc* desc, int32_t* host_out) {
+    std::string why;
+    if (!check_desc(desc, why)) return fail(RMHD_EINVAL, why);
+    if (!host_out) return fail(RMHD_EINVAL, "host_out is NULL");
+    for (int k = 0; k < 3; ++k) host_out[k] = desc->n[k] + 2 * pad_lo(desc, k);
+    return RMHD_OK;
+}
+
 int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes, void* hip_stream, rmhd_ctx** out) {
     std::string why;
     if (!out) return fail(RMHD_EINVAL, "out is null");
@@ -433,7 +451,7 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     std::memset(&p, 0, sizeof p);
     for (int d = 0; d < 3; ++d) {
         p.n[d] = desc->n[d];
-        p.g[d] = ((desc->active_mask >> d) & 1) ? desc->ng : 0;
+        p.g[d] = pad_lo(desc, d);
         p.np[d] = p.n[d] + 2 * p.g[d];
         p.bc[d] = desc->bc[d];
         p.dx[d] = desc->dx[d];
@@ -443,6 +461,7 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     p.st[1] = p.np[0];
     p.st[2] = (long)p.np[0] * p.np[1];
     p.Np = (long)p.np[0] * p.np[1] * p.np[2];
+    p.ng = desc->ng;
     p.active = desc->active_mask;
     p.maxit = desc->c2p_maxit;
     p.speed_mode = desc->speed_mode;

@@ -16,8 +16,10 @@
 
 namespace rmhd {
 
+// g[d]: padded index of the first interior cell along d (the ghost width ng,
+// or more padding along x for aligned rows); np[d] = n[d] + 2 g[d]
 struct Params {
-    int n[3], g[3], np[3], active, bc[3], maxit, speed_mode;
+    int n[3], g[3], np[3], ng, active, bc[3], maxit, speed_mode;
     long st[3], Np;
     double dx[3], idx[3], G, kappa, tol;
     // metric (nullptr alp/gam: flat), beta/K may be nullptr
@@ -356,7 +358,8 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
 // (derivatives from rows c-3..c+1), the current and the reconstruction of c
 // are taken; then row c+3 is requested into the ring slot that row c-2 has
 // just left, and while it arrives the face c-1/2 is computed and rhs row c-1
-// written.  Lanes exchange data only through the ring.
+// written.  Lanes exchange data only through the ring.  Every ring read is
+// preceded by a wait for the loads of its row (the first step included).
 constexpr int WRING = 5;
 
 // all counters but vmcnt at their maxima: wait for every outstanding vector
@@ -466,6 +469,9 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             sources_dir<D>(p, ms, da, db, dg, Pm, Um, acc);
         }
         __builtin_amdgcn_sched_barrier(0);
+        // the first step reads ring row c0 - 1 before its wait below: its
+        // load (issued just before the loop) must have landed first
+        if (c == c0 - 1) wait_ring();
         // current of c (metric and sigma row c: window 3)
         double Jc;
         {
@@ -569,19 +575,20 @@ __global__ void k_any_nonzero(const double* __restrict__ a, long n, unsigned lon
 }
 
 // ---------------------------------------------------------------- ghost fill
-// faces only: ghost layers along each active d, interior extents elsewhere
+// faces only: the ng ghost layers next to the interior along each active d,
+// interior extents elsewhere
 __global__ void k_ghost(const Params p, double* __restrict__ a, int nf, int d) {
     const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
     const long n1 = p.n[e1], n2 = p.n[e2];
-    const long tot = 2L * p.g[d] * n1 * n2;
+    const long tot = 2L * p.ng * n1 * n2;
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= tot) return;
     const int a1 = (int)(t % n1) + p.g[e1];
     t /= n1;
     const int a2 = (int)(t % n2) + p.g[e2];
     t /= n2;
-    const int layer = (int)t;   // 0..2g-1
-    const int c = layer < p.g[d] ? layer : p.n[d] + layer;
+    const int layer = (int)t;   // 0..2ng-1
+    const int c = layer < p.ng ? p.g[d] - p.ng + layer : p.g[d] + p.n[d] + layer - p.ng;
     const int src = bc_map(p, d, c);
     const long ob = (long)a1 * p.st[e1] + (long)a2 * p.st[e2];
     const long od = ob + (long)c * p.st[d], os = ob + (long)src * p.st[d];
@@ -619,6 +626,7 @@ __global__ __launch_bounds__(256) void k_prim2con(const Params p, const double* 
 __device__ __forceinline__ void rec_setup(const Params& p, const Geo<double>& m, const double* U, RecIn& k) {
     k.G = p.G;
     k.D = U[I_D];
+    k.iD = frcp(k.D);          // used only when D > 0
     k.tau = U[I_TAU];
     for (int i = 0; i < 3; ++i) {
         k.S[i] = U[I_S + i];
@@ -857,7 +865,11 @@ struct StageIn {
 };
 
 // STAGE 1: U^n, the (p, v) guess, sigma, metric; 2: + P(1), rhs, R1, K;
-// 3: P(2), U^n, U(2), rhs, R1, R2, metric, K
+// 3: P(2), U^n, U(2), rhs, R1, R2, metric, K.  Without K the local sources
+// need only v and the cleaning fields of P_s, and the guess p and v: the
+// other seven primitives are not loaded (P_LOCAL).
+constexpr int N_LOCAL = 7;
+__device__ constexpr int P_LOCAL[N_LOCAL] = {I_P, I_V, I_V + 1, I_V + 2, I_PHI, I_PSI, I_Q};
 template <int STAGE, bool CURVED, bool HASK>
 __device__ __forceinline__ void stage_load(const Params& p, long t, const double* __restrict__ sig,
                                            const double* __restrict__ Un, const double* __restrict__ Us,
@@ -875,8 +887,13 @@ __device__ __forceinline__ void stage_load(const Params& p, long t, const double
         in.P[I_P] = Ps[I_P * Np + o];
         for (int i = 0; i < 3; ++i) in.P[I_V + i] = Ps[(I_V + i) * Np + o];
     } else {
+        if (HASK) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) in.P[f] = Ps[f * Np + o];
+            for (int f = 0; f < NF; ++f) in.P[f] = Ps[f * Np + o];
+        } else {
+#pragma unroll
+            for (int a = 0; a < N_LOCAL; ++a) in.P[P_LOCAL[a]] = Ps[P_LOCAL[a] * Np + o];
+        }
 #pragma unroll
         for (int f = 0; f < NF; ++f) in.rh[f] = rhs[f * Np + o];
         for (int i = 0; i < 3; ++i) in.R1[i] = R1[i * Np + o];
@@ -950,7 +967,8 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
 // divergence (with the metric-derivative sources) of P_s is in rhs
 template <int STAGE, bool CURVED, bool HASK>
-__device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
+__device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in,
+                                            const double* __restrict__ Ps, double* __restrict__ Uo,
                                             double* __restrict__ Po, double* __restrict__ Ro,
                                             int* __restrict__ status, unsigned long long* nfail) {
     const long Np = p.Np, o = in.o;
@@ -964,7 +982,12 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
         double Y[NF];
         {
             double Uc[NF], S[NF];
-            prim2con(m, p.G, in.P, Uc);
+            if (HASK) {
+                prim2con(m, p.G, in.P, Uc);
+            } else {
+                // the densitised cleaning fields, all the local sources read
+                for (int f = I_PHI; f < NF; ++f) Uc[f] = in.P[f] * m.sg;
+            }
             sources_local<CURVED>(p, m, in.K, CURVED && HASK, in.P, Uc, S);
             if (STAGE == 2) {
                 for (int f = 0; f < NF; ++f) Y[f] = in.Un[f] + dt * (in.rh[f] + S[f]);
@@ -999,7 +1022,8 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     if (st >= 0) {
         write_prims_k(p, o, m, k, cl, x, E, Po);
     } else {
-        for (int f = 0; f < NF; ++f) Po[f * Np + o] = in.P[f];
+        // failed recovery: P_s stands (read again; without K only part of it was loaded)
+        for (int f = 0; f < NF; ++f) Po[f * Np + o] = Ps[f * Np + o];
         for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
         atomicAdd(nfail, 1ull);
     }
@@ -1026,7 +1050,8 @@ __global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const 
     const long nchunk = (ncell + 63) / 64;
     const long W = (long)gridDim.x * (blockDim.x >> 6);
     const int lane = threadIdx.x & 63;
-    long q = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // consecutive chunks on one XCD (shared cache lines at chunk ends)
+    long q = xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
     if (q >= nchunk) return;                                   // uniform per wave
     StageIn in;
     stage_load<STAGE, CURVED, HASK>(p, q * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, in);
@@ -1037,7 +1062,7 @@ __global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const 
         stage_load<STAGE, CURVED, HASK>(p, (qn < nchunk ? qn : q) * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
         if (in.ok) {
             if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Ps, Po, Ro, Uo, status, nfail);
-            else update_cell<STAGE, CURVED, HASK>(p, dt, in, Uo, Po, Ro, status, nfail);
+            else update_cell<STAGE, CURVED, HASK>(p, dt, in, Ps, Uo, Po, Ro, status, nfail);
         }
         if (qn >= nchunk) break;
         q = qn;

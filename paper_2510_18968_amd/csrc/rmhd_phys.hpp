@@ -10,6 +10,7 @@
 // Conserved: D, S_x..z, tau, Bcal^x..z, Ecal^x..z, Phi, Psi, Qcal.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <type_traits>
 
 namespace rmhd {
 
@@ -347,47 +348,39 @@ template <int RECON, class R> __device__ __forceinline__ void recon(const R* s, 
 }
 
 // ---------------------------------------------------------------- recovery
-// 4-direction dual number: value and derivatives w.r.t. (p, v^x, v^y, v^z)
-struct D4 {
-    double v, d[4];
+// 3-direction dual number: value and derivatives with respect to (v^x, v^y,
+// v^z), the velocity columns of the recovery Jacobian in one pass
+struct D3 {
+    double v, d[3];
 };
-__device__ __forceinline__ D4 mk(double v) { return D4{v, {0.0, 0.0, 0.0, 0.0}}; }
-__device__ __forceinline__ D4 operator+(const D4& a, const D4& b) {
-    return D4{a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2], a.d[3] + b.d[3]}};
+__device__ __forceinline__ D3 operator+(const D3& a, const D3& b) {
+    return D3{a.v + b.v, {a.d[0] + b.d[0], a.d[1] + b.d[1], a.d[2] + b.d[2]}};
 }
-__device__ __forceinline__ D4 operator-(const D4& a, const D4& b) {
-    return D4{a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2], a.d[3] - b.d[3]}};
+__device__ __forceinline__ D3 operator-(const D3& a, const D3& b) {
+    return D3{a.v - b.v, {a.d[0] - b.d[0], a.d[1] - b.d[1], a.d[2] - b.d[2]}};
 }
-__device__ __forceinline__ D4 operator*(const D4& a, const D4& b) {
-    return D4{a.v * b.v, {a.d[0] * b.v + a.v * b.d[0], a.d[1] * b.v + a.v * b.d[1], a.d[2] * b.v + a.v * b.d[2],
-                          a.d[3] * b.v + a.v * b.d[3]}};
+__device__ __forceinline__ D3 operator*(const D3& a, const D3& b) {
+    return D3{a.v * b.v, {fma(a.d[0], b.v, a.v * b.d[0]), fma(a.d[1], b.v, a.v * b.d[1]),
+                          fma(a.d[2], b.v, a.v * b.d[2])}};
 }
-__device__ __forceinline__ D4 operator*(double a, const D4& b) {
-    return D4{a * b.v, {a * b.d[0], a * b.d[1], a * b.d[2], a * b.d[3]}};
-}
-__device__ __forceinline__ D4 operator*(const D4& b, double a) { return a * b; }
-__device__ __forceinline__ D4 operator+(const D4& a, double b) { return D4{a.v + b, {a.d[0], a.d[1], a.d[2], a.d[3]}}; }
-__device__ __forceinline__ D4 operator+(double b, const D4& a) { return a + b; }
-__device__ __forceinline__ D4 operator-(const D4& a, double b) { return D4{a.v - b, {a.d[0], a.d[1], a.d[2], a.d[3]}}; }
-__device__ __forceinline__ D4 operator-(double b, const D4& a) {
-    return D4{b - a.v, {-a.d[0], -a.d[1], -a.d[2], -a.d[3]}};
-}
-__device__ __forceinline__ D4 recip(const D4& a) {
+__device__ __forceinline__ D3 operator*(double a, const D3& b) { return D3{a * b.v, {a * b.d[0], a * b.d[1], a * b.d[2]}}; }
+__device__ __forceinline__ D3 operator*(const D3& b, double a) { return a * b; }
+__device__ __forceinline__ D3 operator+(const D3& a, double b) { return D3{a.v + b, {a.d[0], a.d[1], a.d[2]}}; }
+__device__ __forceinline__ D3 operator+(double b, const D3& a) { return a + b; }
+__device__ __forceinline__ D3 operator-(const D3& a, double b) { return D3{a.v - b, {a.d[0], a.d[1], a.d[2]}}; }
+__device__ __forceinline__ D3 operator-(double b, const D3& a) { return D3{b - a.v, {-a.d[0], -a.d[1], -a.d[2]}}; }
+__device__ __forceinline__ D3 inv(const D3& a) {
     const double r = frcp(a.v), r2 = -r * r;
-    return D4{r, {a.d[0] * r2, a.d[1] * r2, a.d[2] * r2, a.d[3] * r2}};
+    return D3{r, {a.d[0] * r2, a.d[1] * r2, a.d[2] * r2}};
 }
-__device__ __forceinline__ D4 operator/(const D4& a, const D4& b) { return a * recip(b); }
-__device__ __forceinline__ D4 operator/(const D4& a, double b) { return a * (1.0 / b); }
-__device__ __forceinline__ D4 operator/(double a, const D4& b) { return a * recip(b); }
-__device__ __forceinline__ D4 rsq(const D4& a) {
+__device__ __forceinline__ D3 rsq(const D3& a) {
     const double r = frsqrt(a.v), h = -0.5 * r * r * r;
-    return D4{r, {a.d[0] * h, a.d[1] * h, a.d[2] * h, a.d[3] * h}};
+    return D3{r, {a.d[0] * h, a.d[1] * h, a.d[2] * h}};
 }
-__device__ __forceinline__ D4 inv(const D4& a) { return recip(a); }
+__device__ __forceinline__ double val(const D3& x) { return x.v; }
 __device__ __forceinline__ double rsq(double a) { return frsqrt(a); }
 __device__ __forceinline__ double inv(double a) { return frcp(a); }
 __device__ __forceinline__ double val(double x) { return x; }
-__device__ __forceinline__ double val(const D4& x) { return x.v; }
 
 // one-direction dual number (value, derivative): Jacobian columns one at a
 // time keep 2 doubles per intermediate instead of 5; also the scalar type of
@@ -438,6 +431,7 @@ __device__ __forceinline__ D1 fmax(const D1& a, const D1& b) { return a.v >= b.v
 template <class T> struct RecInT {
     double G;
     T D, tau, S[3], Bc[3], Bl[3], Es[3], cfac;   // cfac = a dt alpha sigma; Bl = lowered B / sqrt(gamma)
+    T iD;                                        // 1 / D
     double sg, isg, g[6], gi[6];
 };
 using RecIn = RecInT<double>;
@@ -445,9 +439,12 @@ using RecIn = RecInT<double>;
 // Residual of the recovery map at x = (p, v): r0 = (Gamma-1) rho eps - p,
 // r_i = v'^i - v^i, where E solves the implicit stage equation at v
 // (closed form of eq. 3D_NR), v' is the velocity of Sec. III.B step (iii) at
-// (E, p), and rho, eps follow it.  Returns false if unphysical.
+// (E, p), and rho, eps follow it.  Returns false if unphysical.  With S =
+// double and drdp given, also the column dr/dp: at fixed v the field E and
+// the electromagnetic energy do not depend on p, so the column follows from
+// the chain den -> w -> W' -> (rho, eps) by hand.
 template <class S, class K>
-__device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eout) {
+__device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eout, double* drdp = nullptr) {
     const S p = x[0];
     const S v[3] = {x[1], x[2], x[3]};
     S vl[3];
@@ -461,8 +458,12 @@ __device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eo
     b[0] = k.Es[0] - c * (vl[1] * k.Bl[2] - vl[2] * k.Bl[1]);
     b[1] = k.Es[1] - c * (vl[2] * k.Bl[0] - vl[0] * k.Bl[2]);
     b[2] = k.Es[2] - c * (vl[0] * k.Bl[1] - vl[1] * k.Bl[0]);
-    const S vE = (vl[0] * b[0] + vl[1] * b[1] + vl[2] * b[2]) * inv(1.0 + c * (1.0 - v2));
-    const S i1c = inv(1.0 + c);
+    // both denominators from one reciprocal
+    const S a1 = 1.0 + c * (1.0 - v2);
+    const S a2 = 1.0 + c;
+    const S ia = inv(a1 * a2);
+    const S vE = (vl[0] * b[0] + vl[1] * b[1] + vl[2] * b[2]) * (a2 * ia);
+    const S i1c = a1 * ia;
     S E[3];
     for (int i = 0; i < 3; ++i) E[i] = (b[i] + c * vE * v[i]) * i1c;
     S El[3];
@@ -479,15 +480,31 @@ __device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eo
     for (int i = 0; i < 3; ++i) w[i] = k.gi[sidx(i, 0)] * wl[0] + k.gi[sidx(i, 1)] * wl[1] + k.gi[sidx(i, 2)] * wl[2];
     const S w2 = wl[0] * w[0] + wl[1] * w[1] + wl[2] * w[2];
     if (!(val(w2) < 1.0)) return false;
-    const S Wn = rsq(1.0 - w2);
+    const S omw = 1.0 - w2;
+    const S Wn = rsq(omw);
+    const S iW = omw * Wn;                       // 1 / W'
     const S Wn2 = Wn * Wn;
-    const S iW = inv(Wn);
     const S rho = k.D * k.isg * iW;
-    const S eps = (k.tau - k.D * (Wn - 1.0) - k.sg * p * (Wn2 - 1.0) - em) * (iW * inv(k.D));
+    const S num = k.tau - k.D * (Wn - 1.0) - k.sg * p * (Wn2 - 1.0) - em;
+    const S eps = num * (iW * k.iD);
     r[0] = (k.G - 1.0) * rho * eps - p;
     for (int i = 0; i < 3; ++i) r[1 + i] = w[i] - v[i];
     if (Eout)
         for (int i = 0; i < 3; ++i) Eout[i] = E[i];
+    if constexpr (std::is_same<S, double>::value) {
+        if (drdp) {
+            // d(den)/dp = sqrt(gamma): every w_i and w2 scale with 1/den
+            const double s = k.sg * iden;
+            const double w2p = -2.0 * s * w2;
+            const double Wnp = 0.5 * Wn * Wn2 * w2p;
+            const double iWp = -Wnp * iW * iW;
+            const double rhop = k.D * k.isg * iWp;
+            const double nump = -k.D * Wnp - k.sg * (Wn2 - 1.0) - 2.0 * k.sg * p * Wn * Wnp;
+            const double epsp = (nump * iW + num * iWp) * k.iD;
+            drdp[0] = (k.G - 1.0) * (rhop * eps + rho * epsp) - 1.0;
+            for (int i = 0; i < 3; ++i) drdp[1 + i] = -s * w[i];
+        }
+    }
     return isfinite(val(r[0])) && isfinite(val(r[1])) && isfinite(val(r[2])) && isfinite(val(r[3]));
 }
 
@@ -545,24 +562,25 @@ __device__ __forceinline__ void lu4_solve(const double A[4][4], const int* piv, 
 
 enum : int { ST_OK = 0, ST_WARN = 1, ST_NOCONV = -3, ST_UNPHYS = -4 };
 
-// exact Jacobian of the recovery map at x, one dual direction per column,
-// factorised in place; r = residual at x
-// residual r and LU of its Jacobian at x: 0, or JAC_UNPHYS (x outside the
-// physical domain), or JAC_SINGULAR
+// residual r and LU of the exact Jacobian at x (the p column by hand, the v
+// columns by one 3-direction dual pass), factorised in place: JAC_OK, or JAC_UNPHYS (x
+// outside the physical domain), or JAC_SINGULAR
 enum { JAC_OK = 0, JAC_UNPHYS = 1, JAC_SINGULAR = 2 };
 __device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, double J[4][4], int* piv, double* r) {
-#pragma unroll 1
-    for (int b = 0; b < 4; ++b) {
-        D1 xd[4], rd[4];
+    double c0[4];
+    if (!rec_residual<double>(k, x, r, (double*)nullptr, c0)) return JAC_UNPHYS;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) xd[a] = D1{x[a], a == b ? 1.0 : 0.0};
-        if (!rec_residual<D1>(k, xd, rd, (D1*)nullptr)) return JAC_UNPHYS;
+    for (int a = 0; a < 4; ++a) J[a][0] = c0[a];
+    D3 xd[4], rd[4];
+    xd[0] = D3{x[0], {0.0, 0.0, 0.0}};
+    xd[1] = D3{x[1], {1.0, 0.0, 0.0}};
+    xd[2] = D3{x[2], {0.0, 1.0, 0.0}};
+    xd[3] = D3{x[3], {0.0, 0.0, 1.0}};
+    if (!rec_residual<D3>(k, xd, rd, (D3*)nullptr)) return JAC_UNPHYS;
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-            r[a] = rd[a].v;
-            J[a][b] = rd[a].d;
-        }
-    }
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) J[a][1 + b] = rd[a].d[b];
     return lu4(J, piv) ? JAC_OK : JAC_SINGULAR;
 }
 
@@ -573,27 +591,30 @@ __device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, dou
 // physical and the residual decreasing.  x in/out: guess -> (p, v^i);
 // E out: densitised E at the root.
 __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, int maxit, int* iters) {
-    double r[4];
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
-    double J[4][4];
+    double r[4], J[4][4];
     int piv[4];
-    // the Jacobian passes also give the residual at the guess
-    int jst = rec_jacobian(k, x, J, piv, r);
-    if (jst == JAC_UNPHYS) {
-        // guess outside the physical domain: restart at rest with a larger pressure
-        x[1] = x[2] = x[3] = 0.0;
-        bool ok = false;
-        for (int i = 0; i < 64 && !ok; ++i) {
-            ok = rec_residual<double>(k, x, r, (double*)nullptr);
-            if (!ok) x[0] *= 2.0;
-        }
-        if (!ok) { *iters = 0; return ST_UNPHYS; }
-        jst = rec_jacobian(k, x, J, piv, r);
-    }
-    if (jst != JAC_OK) { *iters = 0; return ST_NOCONV; }
-    bool fresh = true;
+    int it = 0, restart = 0;
+    bool need = true, fresh = false;
     double last_rel = 1e300, prev_step = 1e300;
-    for (int it = 1; it <= maxit; ++it) {
+    // one call site each for the Jacobian and the residual keeps the code of
+    // the stage kernels within the instruction cache
+    for (;;) {
+        if (need) {
+            const int jst = rec_jacobian(k, x, J, piv, r);
+            if (jst == JAC_UNPHYS && it == 0 && restart < 64) {
+                // guess outside the physical domain: restart at rest, then
+                // double the pressure until the state is physical
+                if (restart == 0) x[1] = x[2] = x[3] = 0.0;
+                else x[0] *= 2.0;
+                ++restart;
+                continue;
+            }
+            if (jst != JAC_OK) { *iters = it; return (jst == JAC_UNPHYS && it == 0) ? ST_UNPHYS : ST_NOCONV; }
+            need = false;
+            fresh = true;
+        }
+        if (++it > maxit) break;
         double dx[4] = {-r[0], -r[1], -r[2], -r[3]};
         lu4_solve(J, piv, dx);
         const double m0 = rec_merit(r, x[0]);
@@ -610,9 +631,9 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
             t *= 0.5;
         }
         if (!acc) {
+            // a chord step that does not descend: refresh the Jacobian once
             if (fresh) { *iters = it; return ST_NOCONV; }
-            if (rec_jacobian(k, x, J, piv, r) != JAC_OK) { *iters = it; return ST_NOCONV; }
-            fresh = true;
+            need = true;
             continue;
         }
         const double dp = fabs(xt[0] - x[0]);
@@ -622,12 +643,8 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
         last_rel = dp / x[0];
         if (dp <= tol * x[0] && dv <= tol) { *iters = it; return ST_OK; }
         const double step = fmax(last_rel, dv);
-        if (t < 1.0 || step > 0.25 * prev_step) {
-            if (rec_jacobian(k, x, J, piv, r) != JAC_OK) { *iters = it; return ST_NOCONV; }
-            fresh = true;
-        } else {
-            fresh = false;
-        }
+        if (t < 1.0 || step > 0.25 * prev_step) need = true;
+        else fresh = false;
         prev_step = step;
     }
     *iters = maxit;

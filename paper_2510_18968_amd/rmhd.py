@@ -19,7 +19,7 @@ RECON = {"minmod": 0, "mc2": 1, "weno5": 2}
 BC = {"periodic": 0, "copy": 1}
 PREC = {"fp64": 0, "mixed": 1}
 
-SYMBOLS = ("rmhd_workspace_bytes", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
+SYMBOLS = ("rmhd_workspace_bytes", "rmhd_padded_extent", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
            "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
            "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read")
@@ -30,7 +30,7 @@ TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "
 class GridDesc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("active_mask", C.c_int32), ("ng", C.c_int32), ("bc", C.c_int32 * 3),
                 ("recon", C.c_int32), ("precision", C.c_int32), ("c2p_maxit", C.c_int32),
-                ("speed_mode", C.c_int32), ("x0", C.c_double * 3), ("dx", C.c_double * 3),
+                ("speed_mode", C.c_int32), ("x_align", C.c_int32), ("x0", C.c_double * 3), ("dx", C.c_double * 3),
                 ("gamma_ad", C.c_double), ("kappa", C.c_double), ("c2p_tol", C.c_double)]
 
 
@@ -57,6 +57,7 @@ def lib() -> C.CDLL:
         vp, gp = C.c_void_p, C.POINTER(GridDesc)
         sig = {
             "rmhd_workspace_bytes": (C.c_size_t, [gp]),
+            "rmhd_padded_extent": (C.c_int, [gp, C.POINTER(C.c_int32)]),
             "rmhd_init_grid": (C.c_int, [gp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "rmhd_set_metric": (C.c_int, [vp, vp, vp, vp, vp]),
             "rmhd_prim2con": (C.c_int, [vp, vp, vp]),
@@ -89,7 +90,7 @@ def _check(rc: int, what: str):
 
 
 def make_desc(n, active, dx, bc, gamma_ad, recon="weno5", x0=(0.0, 0.0, 0.0), kappa=1.0, precision="fp64",
-              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0) -> GridDesc:
+              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0, x_align=0) -> GridDesc:
     d = GridDesc()
     for k in range(3):
         d.n[k] = int(n[k])
@@ -99,9 +100,48 @@ def make_desc(n, active, dx, bc, gamma_ad, recon="weno5", x0=(0.0, 0.0, 0.0), ka
     d.active_mask, d.ng = int(active), 3
     d.recon = RECON[recon] if isinstance(recon, str) else int(recon)
     d.precision = PREC[precision] if isinstance(precision, str) else int(precision)
-    d.c2p_maxit, d.speed_mode = int(c2p_maxit), int(speed_mode)
+    d.c2p_maxit, d.speed_mode, d.x_align = int(c2p_maxit), int(speed_mode), int(x_align)
     d.gamma_ad, d.kappa, d.c2p_tol = float(gamma_ad), float(kappa), float(c2p_tol)
     return d
+
+
+def padded_extent(desc: GridDesc):
+    """(z, y, x) extents of the padded arrays of a grid, from the library."""
+    e = (C.c_int32 * 3)()
+    _check(lib().rmhd_padded_extent(C.byref(desc), e), "rmhd_padded_extent")
+    return (e[2], e[1], e[0])
+
+
+def std_offsets(desc: GridDesc):
+    """Per axis (z, y, x): how far the library's padding exceeds the 3-cell
+    ghost layout of the workloads and the oracle (nonzero only along x with
+    x_align)."""
+    act = [(desc.active_mask >> k) & 1 for k in range(3)]
+    pad = [(16 if (k == 0 and desc.x_align) else 3) if act[k] else 0 for k in range(3)]
+    std = [3 if act[k] else 0 for k in range(3)]
+    return tuple(pad[k] - std[k] for k in (2, 1, 0))
+
+
+def to_layout(a, desc: GridDesc):
+    """An array in the 3-ghost layout (numpy or torch, trailing axes z, y, x)
+    as a tensor in the grid's layout; the extra padding is zero."""
+    t = torch.as_tensor(a)
+    oz, oy, ox = std_offsets(desc)
+    if (oz, oy, ox) == (0, 0, 0):
+        return t.contiguous()
+    pz, py, px = padded_extent(desc)
+    out = torch.zeros(t.shape[:-3] + (pz, py, px), dtype=t.dtype, device=t.device)
+    out[..., oz:pz - oz, oy:py - oy, ox:px - ox] = t
+    return out
+
+
+def from_layout(t, desc: GridDesc):
+    """A tensor in the grid's layout as a tensor in the 3-ghost layout."""
+    oz, oy, ox = std_offsets(desc)
+    if (oz, oy, ox) == (0, 0, 0):
+        return t
+    pz, py, px = t.shape[-3:]
+    return t[..., oz:pz - oz, oy:py - oy, ox:px - ox].contiguous()
 
 
 class Grid:
@@ -122,9 +162,8 @@ class Grid:
         self._keep = []
         _check(lib().rmhd_init_grid(C.byref(desc), C.c_void_p(self._ws_ptr), nbytes, self._stream(),
                                     C.byref(self._ctx)), "rmhd_init_grid")
-        g = [3 if (desc.active_mask >> k) & 1 else 0 for k in range(3)]
-        self.padded = (desc.n[2] + 2 * g[2], desc.n[1] + 2 * g[1], desc.n[0] + 2 * g[0])
-        self.ghosts = tuple(g)
+        self.padded = padded_extent(desc)
+        self.ghosts = tuple((self.padded[2 - k] - desc.n[k]) // 2 for k in range(3))   # (x, y, z) interior offsets
 
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
@@ -138,6 +177,14 @@ class Grid:
         if tuple(t.shape) != shape:
             raise RMHDError(f"expected shape {shape}, got {tuple(t.shape)}")
         return C.c_void_p(t.data_ptr())
+
+    def to_layout(self, a):
+        """An array of the 3-ghost layout as a device tensor of this grid's layout."""
+        return to_layout(torch.as_tensor(a).to(self.device), self.desc)
+
+    def from_layout(self, t):
+        """A tensor of this grid's layout in the 3-ghost layout."""
+        return from_layout(t, self.desc)
 
     def empty(self, nf=14):
         return torch.zeros((nf,) + self.padded, dtype=torch.float64, device=self.device)

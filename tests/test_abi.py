@@ -47,3 +47,30 @@ def test_descriptor_validation_on_host():
     ctx = C.c_void_p()
     assert L.rmhd_init_grid(C.byref(good), None, 0, None, C.byref(ctx)) == -1
     assert "workspace" in L.rmhd_last_error().decode()
+
+
+@pytest.mark.parametrize("n,active,x_align", [((16, 16, 16), 7, 0), ((256, 256, 256), 7, 1), ((20, 12, 1), 3, 1),
+                                              ((2048, 64, 1), 1, 1), ((400, 1, 1), 1, 0)])
+def test_padded_extent_and_layout_round_trip(n, active, x_align):
+    """The library's padded extents follow the documented layout (3 cells of
+    padding per side on active axes, 16 along x with x_align), and an array
+    of the 3-ghost layout survives the trip into the grid's layout and back."""
+    import numpy as np
+    import torch
+    from paper_2510_18968_amd import rmhd
+    d = rmhd.make_desc(n, active, (0.1,) * 3, (1, 1, 1), 2.0, x_align=x_align)
+    pads = [((16 if (k == 0 and x_align) else 3) if (active >> k) & 1 else 0) for k in range(3)]
+    ext = rmhd.padded_extent(d)
+    assert ext == tuple(n[k] + 2 * pads[k] for k in (2, 1, 0))
+    if x_align:
+        assert ext[2] % 16 == 0 or n[0] % 16 != 0          # aligned rows when n_x is a multiple of 16
+    ws = rmhd.lib().rmhd_workspace_bytes(C.byref(d))
+    assert ws >= 14 * 8 * int(np.prod(ext))
+    if np.prod(ext) > 4e6:
+        return
+    std = tuple(n[k] + 2 * (3 if (active >> k) & 1 else 0) for k in (2, 1, 0))
+    a = torch.from_numpy(np.random.default_rng(3).standard_normal((2,) + std))
+    t = rmhd.to_layout(a, d)
+    assert tuple(t.shape[1:]) == ext
+    assert torch.equal(rmhd.from_layout(t, d), a)
+    assert float(t.abs().sum()) == float(a.abs().sum())    # the extra padding is zero

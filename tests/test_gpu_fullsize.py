@@ -47,12 +47,12 @@ def test_curved_256_stage2_sampled(R, orc, recon):
     then stage 2 on a 7^3 grid whose outer cells are given)."""
     w = W.curved_blob(n=256, recon=recon)
     n, gh = 256, 3
-    # GPU: full grid
-    g = R.grid_for(w)
-    met = dev(w.metric)
+    # GPU: full grid, in the layout the benchmark uses (aligned x rows)
+    g = R.grid_for(w, x_align=1)
+    met = g.to_layout(w.metric)
     g.set_metric(met)
-    sig = dev(w.sigma)
-    P0 = dev(w.P)
+    sig = g.to_layout(w.sigma)
+    P0 = g.to_layout(w.P)
     U0 = g.prim2con(P0)
     P1, R1 = g.empty(), g.empty(3)
     g.imex_stage(1, w.dt, sig, U0, P0, P1, R_out=R1)
@@ -86,7 +86,7 @@ def test_curved_256_stage2_sampled(R, orc, recon):
     # oracle stage 2 on a 7^3 grid per sample
     mg = orc.make_grid((1, 1, 1), 7, w.dx, (2, 2, 2), w.gamma_ad, recon=w.recon)
     gpu_sel = [(slice(None), k + gh, j + gh, i + gh) for (i, j, k) in cells]
-    U2h, P2h, R2h = U2.cpu().numpy(), P2.cpu().numpy(), R2.cpu().numpy()
+    U2h, P2h, R2h = (g.from_layout(t).cpu().numpy() for t in (U2, P2, R2))
     errs = {"U2": [], "P2": [], "R2": []}
     for (i, j, k), gs in zip(cells, gpu_sel):
         c = np.array([k + gh, j + gh, i + gh])
@@ -133,17 +133,17 @@ def test_periodic_box_128_conservation(R):
     """The 128^3 periodic box, 10 IMEX steps: the totals of D, S_i, tau,
     B^i and Q (no sources in flat space, flux form) are conserved."""
     w = W.periodic_box(n=128)
-    g = R.grid_for(w)
-    sig = dev(w.sigma)
-    P = dev(w.P)
+    g = R.grid_for(w, x_align=1)
+    sig = g.to_layout(w.sigma)
+    P = g.to_layout(w.P)
     U = g.prim2con(P)
     I = (slice(None),) + tuple(w.interior)
-    U0 = U[I].cpu().numpy().astype(np.float64)
+    U0 = g.from_layout(U)[I].cpu().numpy().astype(np.float64)
     for _ in range(w.steps):
         g.step(w.dt, sig, U, P)
     torch.cuda.synchronize()
     assert g.failures() == 0
-    U1 = U[I].cpu().numpy()
+    U1 = g.from_layout(U)[I].cpu().numpy()
     for f in (0, 1, 2, 3, 4, 5, 6, 7, 13):
         a, b = U0[f].sum(), U1[f].sum()
         scale = np.abs(U0[f]).sum() + np.abs(U1[f]).sum()
@@ -155,11 +155,11 @@ def test_curved_256_round_trip_after_evolution(R):
     """con2prim(prim2con(P)) = P at full size on the state after 5 steps,
     from a perturbed guess (Sec. III.B recovery, E fixed)."""
     w = W.curved_blob(n=256)
-    g = R.grid_for(w)
-    met = dev(w.metric)
+    g = R.grid_for(w, x_align=1)
+    met = g.to_layout(w.metric)
     g.set_metric(met)
-    sig = dev(w.sigma)
-    P = dev(w.P)
+    sig = g.to_layout(w.sigma)
+    P = g.to_layout(w.P)
     U = g.prim2con(P)
     for _ in range(5):
         g.step(w.dt, sig, U, P)
@@ -172,8 +172,8 @@ def test_curved_256_round_trip_after_evolution(R):
     torch.cuda.synchronize()
     assert g.failures() == 0
     I = tuple(w.interior)
-    assert int((st[I] != 0).sum()) == 0
-    e = rel_errors(guess.cpu().numpy(), P.cpu().numpy(), I)
+    assert int((g.from_layout(st)[I] != 0).sum()) == 0
+    e = rel_errors(g.from_layout(guess).cpu().numpy(), g.from_layout(P).cpu().numpy(), I)
     report("256^3 round trip after 5 steps", e, NAMES_P)
     assert e.max() <= 1e-12
 
@@ -228,3 +228,25 @@ def test_sheet_inversion_64x2048_gradient(R):
     worst, L, gB, gs = inversion_fd_check(R, w, ckpt=20, ndir=8)
     print(f"[rollout] 64x2048 loss {L:.6e} worst rel {worst:.2e}", flush=True)
     assert worst <= 1e-6
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_curved_256_steps_bitwise_reproducible(R, precision):
+    """Three full IMEX steps of the 256^3 workload in the benchmark's layout,
+    twice from the same inputs: bitwise identical states (every ring read of
+    the y/z sweeps waits for its row; no atomics touch the state)."""
+    w = W.curved_blob(n=256)
+    out = []
+    for _ in range(2):
+        g = R.grid_for(w, precision=precision, x_align=1)
+        g.set_metric(g.to_layout(w.metric))
+        sig = g.to_layout(w.sigma)
+        P = g.to_layout(w.P)
+        U = g.prim2con(P)
+        for _ in range(3):
+            g.step(w.dt, sig, U, P)
+        torch.cuda.synchronize()
+        assert g.failures() == 0
+        out.append((g.from_layout(U).cpu(), g.from_layout(P).cpu()))
+        del g, U, P, sig
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])

@@ -86,14 +86,14 @@ def test_con2prim_round_trip_parity(R, orc, name):
     assert rel_errors(P, w.P, I).max() <= TOL
 
 
-def stage_chain_gpu(R, w, dt, sigma_np, P0):
-    g = R.grid_for(w)
+def stage_chain_gpu(R, w, dt, sigma_np, P0, x_align=0):
+    g = R.grid_for(w, x_align=x_align)
     met = None
     if w.metric is not None:
-        met = dev(w.metric)
+        met = g.to_layout(w.metric)
         g.set_metric(met)
-    sig = dev(sigma_np)
-    Pn = dev(P0)
+    sig = g.to_layout(sigma_np)
+    Pn = g.to_layout(P0)
     Un = g.prim2con(Pn)
     P1, R1, U1 = g.empty(), g.empty(3), g.empty()
     g.imex_stage(1, dt, sig, Un, Pn, P1, R_out=R1, U_out=U1)
@@ -101,7 +101,8 @@ def stage_chain_gpu(R, w, dt, sigma_np, P0):
     g.imex_stage(2, dt, sig, Un, P1, P2, R_out=R2, R1=R1, U_out=U2)
     U3, P3 = g.empty(), g.empty()
     g.imex_stage(3, dt, sig, Un, P2, P3, R1=R1, R2=R2, U_s=U2, U_out=U3)
-    out = {k: host(v) for k, v in dict(U0=Un, P1=P1, R1=R1, U1=U1, U2=U2, P2=P2, R2=R2, U3=U3, P3=P3).items()}
+    out = {k: host(g.from_layout(v))
+           for k, v in dict(U0=Un, P1=P1, R1=R1, U1=U1, U2=U2, P2=P2, R2=R2, U3=U3, P3=P3).items()}
     out["nfail"] = g.failures()
     return out
 
@@ -115,14 +116,15 @@ def stage_chain_oracle(orc, og, w, dt, sigma_np, P0):
                 P3=s3["P"], nfail=s1["nfail"] + s2["nfail"] + s3["nfail"])
 
 
+@pytest.mark.parametrize("x_align", [0, 1])
 @pytest.mark.parametrize("name", list(small_workloads().keys()))
-def test_one_step_stagewise_parity(R, orc, name):
+def test_one_step_stagewise_parity(R, orc, name, x_align):
     """Each stage of table imex / eq. IMEX3 (stage 1 implicit, stage 2
     explicit + implicit, final update + recovery) from the same seeded
-    primitives: every intermediate matches the oracle."""
+    primitives: every intermediate matches the oracle, in both x paddings."""
     w = small_workloads()[name]
     og = ogrid(orc, w)
-    gpu = stage_chain_gpu(R, w, w.dt, w.sigma, w.P)
+    gpu = stage_chain_gpu(R, w, w.dt, w.sigma, w.P, x_align)
     ref = stage_chain_oracle(orc, og, w, w.dt, w.sigma, w.P)
     assert gpu["nfail"] == 0 and ref["nfail"] == 0
     I = orc.interior(og)
@@ -137,18 +139,18 @@ def test_one_step_stagewise_parity(R, orc, name):
         assert (e <= tol).all(), (key, e, tol)
 
 
-def run_gpu(R, w, steps):
-    g = R.grid_for(w)
+def run_gpu(R, w, steps, x_align=0):
+    g = R.grid_for(w, x_align=x_align)
     if w.metric is not None:
-        met = dev(w.metric)
+        met = g.to_layout(w.metric)
         g.set_metric(met)
-    sig = dev(w.sigma)
-    P = dev(w.P)
+    sig = g.to_layout(w.sigma)
+    P = g.to_layout(w.P)
     U = g.prim2con(P)
     for _ in range(steps):
         g.step(w.dt, sig, U, P)
     nf = g.failures()
-    return host(U), host(P), nf
+    return host(g.from_layout(U)), host(g.from_layout(P)), nf
 
 
 def run_oracle(orc, w, steps):
@@ -161,12 +163,14 @@ def run_oracle(orc, w, steps):
     return U, P, nf, og
 
 
-@pytest.mark.parametrize("name,steps", [("box12", 2), ("blob20_weno5", 2), ("blob20_mc2", 2),
-                                        ("batch4x128", 3), ("shocktube_s1", 20), ("shocktube_s1e6", 20),
-                                        ("blob16_shift_weno5", 3)])
-def test_multi_step_parity(R, orc, name, steps):
+@pytest.mark.parametrize("name,steps,x_align", [("box12", 2, 0), ("blob20_weno5", 2, 0), ("blob20_mc2", 2, 0),
+                                                ("batch4x128", 3, 0), ("shocktube_s1", 20, 0),
+                                                ("shocktube_s1e6", 20, 0), ("blob16_shift_weno5", 3, 0),
+                                                ("box12", 2, 1), ("blob20_weno5", 2, 1), ("batch4x128", 3, 1),
+                                                ("shocktube_s1e6", 20, 1), ("blob16_shift_weno5", 3, 1)])
+def test_multi_step_parity(R, orc, name, steps, x_align):
     w = small_workloads()[name]
-    U, P, nf = run_gpu(R, w, steps)
+    U, P, nf = run_gpu(R, w, steps, x_align)
     Uo, Po, nfo, og = run_oracle(orc, w, steps)
     assert nf == 0 and nfo == 0
     I = orc.interior(og)
