@@ -21,7 +21,8 @@ struct rmhd_ctx {
     char* ws;
     size_t ws_bytes;
     double *rhs, *P1, *R1, *U2, *P2, *R2;
-    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits, [2] metric scan flag;
+    unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits, [2] metric scan flag,
+                                    // [3] dummy status word;
                                     // [32..127] recovery iteration histograms
     bool curved;
     long persist_blocks = 256;   // persistent flux grid: one 4-wave block per CU, multiple of 8
@@ -221,22 +222,26 @@ int flux_div(rmhd_ctx* c, const double* P, const double* sig) {
     return flux_div_r<double>(c, P, sig);
 }
 
-// persistent stage kernels: one 4-wave block per CU (one wave per SIMD)
+// persistent stage kernels: one one-wave block per SIMD (4 per CU)
 template <int STAGE>
 int launch_stage(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Us, const double* Ps,
                  const double* R1, const double* R2, double* Uo, double* Po, double* Ro, int32_t* st) {
-    const long nchunk = (ncells(c->p) + 63) / 64;
+    const Params& p = c->p;
+    const long nchunk = (long)((p.n[0] + 63) / 64) * p.n[1] * p.n[2];
     // a multiple of 8, so that the XCD renumbering of the blocks is a bijection
-    const long blocks = std::min<long>(c->persist_blocks, ((nchunk + 3) / 4 + 7) / 8 * 8);
+    const long blocks = std::min<long>(4 * c->persist_blocks, (nchunk + 7) / 8 * 8);
+    // without a status array every cell writes one dummy word (counters[3])
+    int32_t* sp = st ? st : reinterpret_cast<int32_t*>(c->counters + 3);
+    const long ss = st ? 1 : 0;
     if (c->curved && c->p.K)
-        k_stage<STAGE, true, true><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                   Ro, st, c->counters);
+        k_stage<STAGE, true, true><<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                   Ro, sp, ss, c->counters);
     else if (c->curved)
-        k_stage<STAGE, true, false><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                    Ro, st, c->counters);
+        k_stage<STAGE, true, false><<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                    Ro, sp, ss, c->counters);
     else
-        k_stage<STAGE, false, false><<<blocks, 256, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                     Ro, st, c->counters);
+        k_stage<STAGE, false, false><<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
+                                                                     Ro, sp, ss, c->counters);
     LAUNCH_CHECK();
     return RMHD_OK;
 }

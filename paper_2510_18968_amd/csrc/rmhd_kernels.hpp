@@ -839,19 +839,18 @@ __device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m,
 // gamma of table imex
 __host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560; }
 
-// recovery iteration histogram: one atomic per distinct count in the wave
-// (called by the active lanes that ran a recovery)
-__device__ __forceinline__ void hist_add(unsigned long long* hist, int it) {
-    const int v = it < 0 ? 0 : (it > 31 ? 31 : it);
-    const int lane = threadIdx.x & 63;
-    unsigned long long todo = __ballot(1);
-    while (todo) {
-        const int leader = __ffsll(todo) - 1;
-        const int val = __shfl(v, leader);
-        const unsigned long long m = __ballot(v == val);
-        if (lane == leader) atomicAdd(hist + val, (unsigned long long)__popcll(m));
-        todo &= ~m;
-    }
+// per-block tallies of the stage kernels in LDS (recovery iteration
+// histogram, failed cells), added to the global counters once per block at
+// the end: inside the chunk loop no global atomic sits between the next
+// chunk's loads and the wait for them
+struct StageTally {
+    unsigned int hist[32];
+    unsigned int fail;
+};
+__device__ __forceinline__ void tally_cell(StageTally& t, bool hist, bool counted, int st, int it) {
+    if (!counted) return;
+    if (hist) atomicAdd(&t.hist[it < 0 ? 0 : (it > 31 ? 31 : it)], 1u);
+    if (st < 0) atomicAdd(&t.fail, 1u);
 }
 
 // ---------------------------------------------------------- stage kernels
@@ -864,53 +863,148 @@ struct StageIn {
     double P[NF], Un[NF], rh[NF], Us[NF], R1[3], R2[3], sg, a, g[6], K[6];
 };
 
-// STAGE 1: U^n, the (p, v) guess, sigma, metric; 2: + P(1), rhs, R1, K;
-// 3: P(2), U^n, U(2), rhs, R1, R2, metric, K.  Without K the local sources
-// need only v and the cleaning fields of P_s, and the guess p and v: the
-// other seven primitives are not loaded (P_LOCAL).
-constexpr int N_LOCAL = 7;
-__device__ constexpr int P_LOCAL[N_LOCAL] = {I_P, I_V, I_V + 1, I_V + 2, I_PHI, I_PSI, I_Q};
-template <int STAGE, bool CURVED, bool HASK>
-__device__ __forceinline__ void stage_load(const Params& p, long t, const double* __restrict__ sig,
-                                           const double* __restrict__ Un, const double* __restrict__ Us,
-                                           const double* __restrict__ Ps, const double* __restrict__ R1,
-                                           const double* __restrict__ R2, const double* __restrict__ rhs, StageIn& in) {
-    // branch-free: a lane past the last cell loads the last cell (ok = false),
-    // so that the wait-count pass sees the same loads in flight on every path
-    const long ncell = (long)p.n[0] * p.n[1] * p.n[2];
-    in.ok = t < ncell;
-    interior_cell(p, in.ok ? t : ncell - 1, in.o);
-    const long Np = p.Np, o = in.o;
-#pragma unroll
-    for (int f = 0; f < NF; ++f) in.Un[f] = Un[f * Np + o];
+// Inputs of a stage kernel as a list of streams (array, field), each one
+// [Np] row of doubles.  STAGE 1: U^n, the (p, v) guess, sigma, metric;
+// 2: + P(1), rhs, R1, K; 3: P(2), U^n, U(2), rhs, R1, R2, metric, K.
+// Without K the local sources need only v and the cleaning fields of P_s,
+// and the guess p and v: the other seven primitives are not loaded.
+enum : int { SA_UN, SA_US, SA_PS, SA_R1, SA_R2, SA_RHS, SA_SIG, SA_ALP, SA_GAM, SA_K };
+struct StreamList {
+    int n;
+    int s[80];                                   // array * 32 + field
+};
+template <int STAGE, bool CURVED, bool HASK> __host__ __device__ constexpr StreamList stage_streams() {
+    StreamList L{0, {}};
+    auto add = [&L](int a, int f) { L.s[L.n++] = a * 32 + f; };
+    for (int f = 0; f < NF; ++f) add(SA_UN, f);
     if (STAGE == 1) {
-        in.P[I_P] = Ps[I_P * Np + o];
-        for (int i = 0; i < 3; ++i) in.P[I_V + i] = Ps[(I_V + i) * Np + o];
+        for (int f = I_P; f < I_V + 3; ++f) add(SA_PS, f);
     } else {
         if (HASK) {
-#pragma unroll
-            for (int f = 0; f < NF; ++f) in.P[f] = Ps[f * Np + o];
+            for (int f = 0; f < NF; ++f) add(SA_PS, f);
         } else {
-#pragma unroll
-            for (int a = 0; a < N_LOCAL; ++a) in.P[P_LOCAL[a]] = Ps[P_LOCAL[a] * Np + o];
+            for (int f = I_P; f < I_V + 3; ++f) add(SA_PS, f);
+            for (int f = I_PHI; f < NF; ++f) add(SA_PS, f);
         }
+        for (int f = 0; f < NF; ++f) add(SA_RHS, f);
+        for (int i = 0; i < 3; ++i) add(SA_R1, i);
+    }
+    if (STAGE == 3) {
+        for (int f = 0; f < NF; ++f) add(SA_US, f);
+        for (int i = 0; i < 3; ++i) add(SA_R2, i);
+    } else {
+        add(SA_SIG, 0);
+    }
+    if (CURVED) {
+        add(SA_ALP, 0);
+        for (int a = 0; a < 6; ++a) add(SA_GAM, a);
+        if (STAGE != 1 && HASK)
+            for (int a = 0; a < 6; ++a) add(SA_K, a);
+    }
+    if (L.n & 1) add(L.s[L.n - 1] / 32, L.s[L.n - 1] % 32);   // even: two streams per load instruction
+    return L;
+}
+// position of stream (a, f) in the list (-1: not there)
+template <int STAGE, bool CURVED, bool HASK> __device__ constexpr int stream_pos(int a, int f) {
+    constexpr StreamList L = stage_streams<STAGE, CURVED, HASK>();
+    for (int i = 0; i < L.n; ++i)
+        if (L.s[i] == a * 32 + f) return i;
+    return -1;
+}
+
+struct StageArrays {
+    const double *Un, *Us, *Ps, *R1, *R2, *rhs, *sig;
+};
+__device__ __forceinline__ const double* stream_ptr(const Params& p, const StageArrays& A, int s) {
+    const int a = s / 32, f = s % 32;
+    const double* b = a == SA_UN ? A.Un : a == SA_US ? A.Us : a == SA_PS ? A.Ps : a == SA_R1 ? A.R1
+                    : a == SA_R2 ? A.R2 : a == SA_RHS ? A.rhs : a == SA_SIG ? A.sig : a == SA_ALP ? p.alp
+                    : a == SA_GAM ? p.gam : p.K;
+    return b + (long)f * p.Np;
+}
+
+// s_waitcnt with vmcnt(N) and the other counters at their maxima
+template <int N> __device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt has six bits");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
+// s_waitcnt lgkmcnt(0) (LDS reads landed), the other counters at their maxima
+__device__ __forceinline__ void wait_lgkm0() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
+
+// A chunk is 64 consecutive cells of one interior x row: chunk q is segment
+// q mod nsx of row q / nsx (rows y fastest, then z).
+struct Chunk {
+    long orow;     // padded offset of the row's first interior cell
+    int x0;        // interior x of the chunk's first cell
+};
+__device__ __forceinline__ Chunk chunk_at(const Params& p, long q, int nsx) {
+    const long r = q / nsx;
+    const int seg = (int)(q - r * nsx);
+    const long j = r % p.n[1], k = r / p.n[1];
+    return Chunk{(k + p.g[2]) * p.st[2] + (j + p.g[1]) * p.st[1] + p.g[0], seg * 64};
+}
+
+// Ask for chunk c's streams straight into the wave's LDS buffer
+// (global_load_lds_dwordx4: lane m brings cells 2(m mod 32), +1 of stream
+// 2i + m / 32; the pair is clamped inside the padded row, a pair past the
+// row's end is never read).
+template <int STAGE, bool CURVED, bool HASK>
+__device__ __forceinline__ void stage_issue(const Params& p, const StageArrays& A, const Chunk& c, double* buf,
+                                            int lane) {
+    constexpr StreamList L = stage_streams<STAGE, CURVED, HASK>();
+    const long xp = min((long)(c.x0 + 2 * (lane & 31)), (long)(p.np[0] - 2 - p.g[0]));
+    const long oo = c.orow + xp;
+    const bool hi = lane >= 32;
 #pragma unroll
-        for (int f = 0; f < NF; ++f) in.rh[f] = rhs[f * Np + o];
-        for (int i = 0; i < 3; ++i) in.R1[i] = R1[i * Np + o];
+    for (int i = 0; i < L.n / 2; ++i) {
+        // select the lane's stream as an integer (a select of two pointers
+        // may be lowered through a stack slot)
+        const unsigned long long a = (unsigned long long)stream_ptr(p, A, L.s[2 * i]);
+        const unsigned long long b = (unsigned long long)stream_ptr(p, A, L.s[2 * i + 1]);
+        const double* src = (const double*)(hi ? b : a) + oo;
+        __builtin_amdgcn_global_load_lds((const void*)src, (__attribute__((address_space(3))) void*)(buf + 2 * i * 64),
+                                         16, 0, 0);
+    }
+}
+
+// The lane's inputs from the LDS buffer.  A lane past the row's end reads the
+// row's last cell (ok = false): it repeats that cell's arithmetic and stores.
+template <int STAGE, bool CURVED, bool HASK>
+__device__ __forceinline__ void stage_read(const Params& p, const Chunk& c, const double* buf, int lane, StageIn& in) {
+    in.ok = c.x0 + lane < p.n[0];
+    const int lc = in.ok ? lane : p.n[0] - 1 - c.x0;
+    in.o = c.orow + c.x0 + lc;
+    auto rd = [&](int a, int f) -> double {
+        const int i = stream_pos<STAGE, CURVED, HASK>(a, f);
+        return i < 0 ? 0.0 : buf[i * 64 + lc];
+    };
+#pragma unroll
+    for (int f = 0; f < NF; ++f) in.Un[f] = rd(SA_UN, f);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) in.P[f] = rd(SA_PS, f);
+    if (STAGE != 1) {
+#pragma unroll
+        for (int f = 0; f < NF; ++f) in.rh[f] = rd(SA_RHS, f);
+        for (int i = 0; i < 3; ++i) in.R1[i] = rd(SA_R1, i);
     }
     if (STAGE == 3) {
 #pragma unroll
-        for (int f = 0; f < NF; ++f) in.Us[f] = Us[f * Np + o];
-        for (int i = 0; i < 3; ++i) in.R2[i] = R2[i * Np + o];
+        for (int f = 0; f < NF; ++f) in.Us[f] = rd(SA_US, f);
+        for (int i = 0; i < 3; ++i) in.R2[i] = rd(SA_R2, i);
     } else {
-        in.sg = sig[o];
+        in.sg = rd(SA_SIG, 0);
     }
     if (CURVED) {
-        in.a = p.alp[o];
-#pragma unroll
-        for (int a = 0; a < 6; ++a) in.g[a] = p.gam[a * Np + o];
+        in.a = rd(SA_ALP, 0);
+        for (int a = 0; a < 6; ++a) in.g[a] = rd(SA_GAM, a);
         if (STAGE != 1 && HASK)
-            for (int a = 0; a < 6; ++a) in.K[a] = p.K[a * Np + o];
+            for (int a = 0; a < 6; ++a) in.K[a] = rd(SA_K, a);
     }
 }
 
@@ -926,12 +1020,13 @@ template <bool CURVED> __device__ __forceinline__ void stage_geo(const StageIn& 
     }
 }
 
-// stage 1: E(1) = E^n + gamma dt R_E(U(1)), everything else unchanged
+// stage 1: E(1) = E^n + gamma dt R_E(U(1)), everything else unchanged.  A
+// failed cell (flagged in status and the failure count) is written as the
+// primitives of U^n at the guess's p and v with E = E^n.
 template <bool CURVED>
-__device__ __forceinline__ void stage1_cell(const Params& p, double dt, const StageIn& in,
-                                            const double* __restrict__ Pg_, double* __restrict__ P1,
+__device__ __forceinline__ void stage1_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ P1,
                                             double* __restrict__ R1, double* __restrict__ U1,
-                                            int* __restrict__ status, unsigned long long* nfail) {
+                                            int* __restrict__ status, long st_stride, StageTally& tal) {
     const long Np = p.Np, o = in.o;
     Geo<double> m;
     stage_geo<CURVED>(in, m);
@@ -950,27 +1045,24 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
     if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
     else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     __builtin_amdgcn_sched_barrier(0);
-    if (p.hist) hist_add(p.hist, it);                        // stage 1: bins 0..31
-    if (st >= 0) {
-        write_prims_k(p, o, m, k, in.Un + I_PHI, x, E, P1);
-    } else {
-        for (int f = 0; f < NF; ++f) P1[f * Np + o] = Pg_[f * Np + o];
-        for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
-        atomicAdd(nfail, 1ull);
+    tally_cell(tal, p.hist != nullptr, in.ok, st, it);
+    if (st < 0) {
+        x[0] = in.P[I_P];
+        for (int i = 0; i < 3; ++i) { x[1 + i] = in.P[I_V + i]; E[i] = k.Es[i]; }
     }
+    write_prims_k(p, o, m, k, in.Un + I_PHI, x, E, P1);
     for (int i = 0; i < 3; ++i) R1[i * Np + o] = (E[i] - k.Es[i]) / gdt;
     if (U1)
         for (int i = 0; i < 3; ++i) U1[(I_E + i) * Np + o] = E[i];
-    if (status) status[o] = st;
+    status[st_stride * o] = st;
 }
 
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
 // divergence (with the metric-derivative sources) of P_s is in rhs
 template <int STAGE, bool CURVED, bool HASK>
-__device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in,
-                                            const double* __restrict__ Ps, double* __restrict__ Uo,
+__device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
                                             double* __restrict__ Po, double* __restrict__ Ro,
-                                            int* __restrict__ status, unsigned long long* nfail) {
+                                            int* __restrict__ status, long st_stride, StageTally& tal) {
     const long Np = p.Np, o = in.o;
     Geo<double> m;
     stage_geo<CURVED>(in, m);
@@ -1018,56 +1110,83 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
         st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     }
     __builtin_amdgcn_sched_barrier(0);
-    if (p.hist) hist_add(p.hist + (STAGE == 2 ? 32 : 64), it);   // stage 2: 32..63, final: 64..95
-    if (st >= 0) {
-        write_prims_k(p, o, m, k, cl, x, E, Po);
-    } else {
-        // failed recovery: P_s stands (read again; without K only part of it was loaded)
-        for (int f = 0; f < NF; ++f) Po[f * Np + o] = Ps[f * Np + o];
-        for (int i = 0; i < 3; ++i) E[i] = k.Es[i];
-        atomicAdd(nfail, 1ull);
+    tally_cell(tal, p.hist != nullptr, in.ok, st, it);
+    if (st < 0) {
+        // failed (flagged): the primitives of the stage state at the guess's
+        // p and v with E = E*; every store below is taken on every path
+        x[0] = in.P[I_P];
+        for (int i = 0; i < 3; ++i) { x[1 + i] = in.P[I_V + i]; E[i] = k.Es[i]; }
     }
+    write_prims_k(p, o, m, k, cl, x, E, Po);
     if (STAGE == 2) {
         for (int i = 0; i < 3; ++i) {
             Uo[(I_E + i) * Np + o] = E[i];
             Ro[i * Np + o] = (E[i] - k.Es[i]) / (g * dt);
         }
     }
-    if (status) status[o] = st;
+    status[st_stride * o] = st;
 }
 
+// stores of one chunk per lane: every one is taken on every path
+template <int STAGE> constexpr int stage_stores() { return STAGE == 1 ? 18 : (STAGE == 2 ? 32 : 29); }
+
 // STAGE 1: stage1_cell (Us, R2, rhs unused; Ps = the guess, Uo = U1, Ro = R1)
-// STAGE 2, 3: update_cell.  HASK: nonzero extrinsic curvature.
+// STAGE 2, 3: update_cell.  HASK: nonzero extrinsic curvature.  status is
+// written at status[st_stride * o] (st_stride 0: one dummy word).
+// Persistent, one wave per block (and per SIMD: the recovery's registers
+// allow no more), walking chunks q, q + W, ...  The next chunk's inputs are
+// loaded into the wave's LDS buffer while the current chunk (read from it
+// into registers first) is computed and stored; the wait for them leaves the
+// current chunk's stores in flight (stage 1 stores 18 or 32 per chunk, so
+// waiting for 18 is safe in both cases).
 template <int STAGE, bool CURVED, bool HASK>
-__global__ __launch_bounds__(256) void k_stage(const Params p, double dt, const double* __restrict__ sig,
-                                               const double* __restrict__ Un, const double* __restrict__ Us,
-                                               const double* __restrict__ Ps, const double* __restrict__ R1,
-                                               const double* __restrict__ R2, const double* __restrict__ rhs,
-                                               double* __restrict__ Uo, double* __restrict__ Po,
-                                               double* __restrict__ Ro, int* __restrict__ status,
-                                               unsigned long long* nfail) {
-    const long ncell = (long)p.n[0] * p.n[1] * p.n[2];
-    const long nchunk = (ncell + 63) / 64;
-    const long W = (long)gridDim.x * (blockDim.x >> 6);
-    const int lane = threadIdx.x & 63;
+__global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const double* __restrict__ sig,
+                                              const double* __restrict__ Un, const double* __restrict__ Us,
+                                              const double* __restrict__ Ps, const double* __restrict__ R1,
+                                              const double* __restrict__ R2, const double* __restrict__ rhs,
+                                              double* __restrict__ Uo, double* __restrict__ Po,
+                                              double* __restrict__ Ro, int* __restrict__ status, long st_stride,
+                                              unsigned long long* nfail) {
+    constexpr int NS = stage_streams<STAGE, CURVED, HASK>().n;
+    static_assert(NS <= 80 && NS % 2 == 0, "stream list");
+    __shared__ double buf[NS * 64];
+    __shared__ StageTally tal;
+    const int lane = threadIdx.x;
+    if (lane < 32) tal.hist[lane] = 0u;
+    if (lane == 0) tal.fail = 0u;
+    const int nsx = (p.n[0] + 63) / 64;
+    const long nchunk = (long)nsx * p.n[1] * p.n[2];
+    const long W = gridDim.x;
+    const StageArrays A{Un, Us, Ps, R1, R2, rhs, sig};
     // consecutive chunks on one XCD (shared cache lines at chunk ends)
-    long q = xcd_block() * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (q >= nchunk) return;                                   // uniform per wave
-    StageIn in;
-    stage_load<STAGE, CURVED, HASK>(p, q * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, in);
-    for (;;) {
-        const long qn = q + W;
-        // unconditional (the last pass reloads its own chunk)
-        StageIn nx;
-        stage_load<STAGE, CURVED, HASK>(p, (qn < nchunk ? qn : q) * 64 + lane, sig, Un, Us, Ps, R1, R2, rhs, nx);
-        if (in.ok) {
-            if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Ps, Po, Ro, Uo, status, nfail);
-            else update_cell<STAGE, CURVED, HASK>(p, dt, in, Ps, Uo, Po, Ro, status, nfail);
+    long q = xcd_block();
+    if (q < nchunk) {                                          // uniform per wave
+        Chunk c = chunk_at(p, q, nsx);
+        stage_issue<STAGE, CURVED, HASK>(p, A, c, buf, lane);
+        wait_vm<0>();
+        for (;;) {
+            StageIn in;
+            stage_read<STAGE, CURVED, HASK>(p, c, buf, lane, in);
+            wait_lgkm0();                                      // the buffer is free again
+            const long qn = q + W;
+            const Chunk cn = chunk_at(p, qn < nchunk ? qn : q, nsx);
+            // unconditional (the last pass reloads its own chunk)
+            stage_issue<STAGE, CURVED, HASK>(p, A, cn, buf, lane);
+            if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Po, Ro, Uo, status, st_stride, tal);
+            else update_cell<STAGE, CURVED, HASK>(p, dt, in, Uo, Po, Ro, status, st_stride, tal);
+            // the loads above were followed by this chunk's stores only
+            wait_vm<stage_stores<STAGE>()>();
+            if (qn >= nchunk) break;
+            q = qn;
+            c = cn;
         }
-        if (qn >= nchunk) break;
-        q = qn;
-        in = nx;
+        wait_vm<0>();                                          // no load into LDS in flight at the end
     }
+    __syncthreads();
+    // histogram bins: stage 1 0..31, stage 2 32..63, final 64..95
+    if (p.hist && lane < 32 && tal.hist[lane])
+        atomicAdd(p.hist + 32 * (STAGE - 1) + lane, (unsigned long long)tal.hist[lane]);
+    if (lane == 0 && tal.fail) atomicAdd(nfail, (unsigned long long)tal.fail);
 }
 
 // ---------------------------------------------------- max signal speed (CFL)

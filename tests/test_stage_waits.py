@@ -1,0 +1,52 @@
+"""The stage kernels load the next chunk into LDS and then wait with
+s_waitcnt vmcnt(N), N = the stores of the current chunk, so that those stores
+stay in flight.  That wait is only safe if every path from the last load into
+LDS to the wait issues at least N vector-memory instructions (vmcnt counts
+them in order).  Compiles the kernels for gfx950 and checks it on the
+control-flow graph of their assembly (no device needed)."""
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from asmcheck.vmcount import kernels, path_counts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+
+@pytest.fixture(scope="module")
+def asm(tmp_path_factory):
+    if not os.path.exists(HIPCC) and not shutil.which("hipcc"):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("asm") / "stage.s"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+           "-packed-fp32-ops", "-Wno-unused-command-line-argument", "-I", os.path.join(ROOT, "include"),
+           "-I", os.path.join(ROOT, "paper_2510_18968_amd", "csrc"), "--cuda-device-only", "-S",
+           os.path.join(ROOT, "tests", "asmcheck", "stage_kernels.hip"), "-o", str(out)]
+    subprocess.run(cmd, check=True, capture_output=True)
+    return kernels(out.read_text())
+
+
+def test_stage_kernel_waits_cover_their_loads(asm):
+    ks = {k: v for k, v in asm.items() if "k_stage" in k}
+    assert len(ks) == 9
+    for name, L in ks.items():
+        lds = [i for i, l in enumerate(L) if "global_load_lds_dwordx4" in l]
+        waits = [(i, int(m.group(1))) for i, l in enumerate(L)
+                 for m in [re.search(r's_waitcnt vmcnt\((\d+)\)', l)] if m and int(m.group(1)) > 0]
+        assert lds and waits, name
+        # the loop's loads are the last block of loads into LDS; its wait is the
+        # first nonzero vmcnt wait reachable from them
+        last = lds[-1]
+        checked = 0
+        for wi, n in waits:
+            lo, hi = path_counts(L, last + 1, wi)
+            if lo is None:
+                continue
+            print(f"{name[:40]}: vmcnt({n}) after the loads into LDS: {lo}..{hi} vector-memory ops on the way")
+            assert lo >= n, (name, n, lo)
+            checked += 1
+        assert checked >= 1, name
