@@ -118,6 +118,20 @@ __device__ __forceinline__ long xcd_block() {
     return (long)(b & 7u) * (long)(nb >> 3) + (long)(b >> 3);
 }
 
+// s_waitcnt with vmcnt(N) and the other counters at their maxima
+template <int N> __device__ __forceinline__ void wait_vm() {
+    static_assert(N >= 0 && N < 64, "vmcnt has six bits");
+    __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
+// s_waitcnt lgkmcnt(0) (LDS reads landed), the other counters at their maxima
+__device__ __forceinline__ void wait_lgkm0() {
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("" ::: "memory");
+}
+
 // v, with a data dependency on dep: keeps the compiler from hoisting the lane
 // shuffles of v above the work that produced dep (which would keep every
 // field's stencil live at once)
@@ -298,10 +312,14 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
         sources_dir<D>(p, mc, da, db, dg, in.P, Uc, acc);
     }
     const R ih = R(p.idx[D]);
+    // every lane stores (no branch: the wait for the next segment's loads can
+    // then leave these stores in flight); a lane without a cell of its own
+    // writes the line's last left ghost cell, which nothing reads in rhs
+    const long os = cell ? o : o - (long)(it.cp - (gD - 1)) * s;
 #pragma unroll
     for (int f = 0; f < NF; ++f) {
         const R Fl = up<1>(Fh[f]);
-        if (cell) rhs[f * Np + o] = acc[f] + double(-(Fh[f] - Fl) * ih);
+        rhs[f * Np + os] = acc[f] + double(-(Fh[f] - Fl) * ih);
     }
 }
 
@@ -332,6 +350,9 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
     FluxItem<D> it = flux_item<D>(p, wid, nseg, lane);
     FluxIn in;
     flux_load<D, CURVED>(p, P, sig, it, in);
+    // the loop begins with every input loaded on both ways into it, so the
+    // wait-count pass needs no wait on them inside
+    if (!ACC) wait_vm<0>();
     for (;;) {
         const long nxt = wid + W;
         // unconditional (the last pass reloads a valid item): a branch around
@@ -341,6 +362,9 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
         FluxIn in2;
         flux_load<D, CURVED>(p, P, sig, it2, in2);
         flux_compute<D, RECON, CURVED, R, ACC>(p, P, rhs, it, in, lane);
+        // the next segment's loads were followed by the NF stores of this one
+        // only: wait for the loads, leave the stores in flight
+        if (!ACC) wait_vm<NF>();
         if (nxt >= nitems) break;
         wid = nxt;
         it = it2;
@@ -923,19 +947,6 @@ __device__ __forceinline__ const double* stream_ptr(const Params& p, const Stage
     return b + (long)f * p.Np;
 }
 
-// s_waitcnt with vmcnt(N) and the other counters at their maxima
-template <int N> __device__ __forceinline__ void wait_vm() {
-    static_assert(N >= 0 && N < 64, "vmcnt has six bits");
-    __builtin_amdgcn_s_waitcnt(0x0F70 | (N & 15) | ((N >> 4) << 14));
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("" ::: "memory");
-}
-// s_waitcnt lgkmcnt(0) (LDS reads landed), the other counters at their maxima
-__device__ __forceinline__ void wait_lgkm0() {
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    __builtin_amdgcn_sched_barrier(0);
-    asm volatile("" ::: "memory");
-}
 
 // A chunk is 64 consecutive cells of one interior x row: chunk q is segment
 // q mod nsx of row q / nsx (rows y fastest, then z).

@@ -1,4 +1,5 @@
-// Instantiates every stage kernel so that its gfx950 assembly can be checked
+// Instantiates every stage kernel and the FP64 x-flux kernels so that their
+// gfx950 assembly can be checked
 // (tests/test_stage_waits.py); never linked into the library.
 #include <hip/hip_runtime.h>
 #include "rmhd_kernels.hpp"
@@ -6,7 +7,12 @@ using namespace rmhd;
 template <int S, bool C, bool K> void inst(const Params& p, double* a, unsigned long long* c, int* s) {
     k_stage<S, C, K><<<1, 64>>>(p, 0.1, a, a, a, a, a, a, a, a, a, a, s, 1L, c);
 }
+template <int RC, bool C> void inst_x(const Params& p, double* a) {
+    k_flux_p<0, RC, C, double, false><<<8, 256>>>(p, a, a, a, 1, 1L);
+}
 void all(const Params& p, double* a, unsigned long long* c, int* s) {
+    inst_x<0, false>(p, a); inst_x<1, false>(p, a); inst_x<2, false>(p, a);
+    inst_x<0, true>(p, a); inst_x<1, true>(p, a); inst_x<2, true>(p, a);
     inst<1, false, false>(p, a, c, s); inst<1, true, false>(p, a, c, s); inst<1, true, true>(p, a, c, s);
     inst<2, false, false>(p, a, c, s); inst<2, true, false>(p, a, c, s); inst<2, true, true>(p, a, c, s);
     inst<3, false, false>(p, a, c, s); inst<3, true, false>(p, a, c, s); inst<3, true, true>(p, a, c, s);

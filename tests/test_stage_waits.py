@@ -1,6 +1,7 @@
-"""The stage kernels load the next chunk into LDS and then wait with
-s_waitcnt vmcnt(N), N = the stores of the current chunk, so that those stores
-stay in flight.  That wait is only safe if every path from the last load into
+"""The stage kernels load the next chunk into LDS, the FP64 x-flux kernels
+the next segment into registers, and both then wait with s_waitcnt vmcnt(N),
+N = the stores of the current chunk or segment, so that those stores stay in
+flight.  That wait is only safe if every path from the last load into
 LDS to the wait issues at least N vector-memory instructions (vmcnt counts
 them in order).  Compiles the kernels for gfx950 and checks it on the
 control-flow graph of their assembly (no device needed)."""
@@ -30,23 +31,25 @@ def asm(tmp_path_factory):
     return kernels(out.read_text())
 
 
-def test_stage_kernel_waits_cover_their_loads(asm):
-    ks = {k: v for k, v in asm.items() if "k_stage" in k}
-    assert len(ks) == 9
+@pytest.mark.parametrize("kind,count,load", [("k_stage", 9, "global_load_lds_dwordx4"),
+                                             ("k_flux_p", 6, "global_load_dwordx2")])
+def test_kernel_waits_cover_their_loads(asm, kind, count, load):
+    ks = {k: v for k, v in asm.items() if kind in k}
+    assert len(ks) == count
     for name, L in ks.items():
-        lds = [i for i, l in enumerate(L) if "global_load_lds_dwordx4" in l]
+        lds = [i for i, l in enumerate(L) if load in l]
         waits = [(i, int(m.group(1))) for i, l in enumerate(L)
                  for m in [re.search(r's_waitcnt vmcnt\((\d+)\)', l)] if m and int(m.group(1)) > 0]
         assert lds and waits, name
-        # the loop's loads are the last block of loads into LDS; its wait is the
-        # first nonzero vmcnt wait reachable from them
+        # the loop's loads are the last block of loads; every nonzero vmcnt
+        # wait reachable from them must be covered
         last = lds[-1]
         checked = 0
         for wi, n in waits:
             lo, hi = path_counts(L, last + 1, wi)
             if lo is None:
                 continue
-            print(f"{name[:40]}: vmcnt({n}) after the loads into LDS: {lo}..{hi} vector-memory ops on the way")
+            print(f"{name[:40]}: vmcnt({n}) after the loop loads: {lo}..{hi} vector-memory ops on the way")
             assert lo >= n, (name, n, lo)
             checked += 1
         assert checked >= 1, name
