@@ -460,20 +460,31 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         if (c >= -gD) load_metric(c, wa[k], bk, wg[k], ws[k]);
     }
 
+    // every step issues the same memory operations in the same order (rhs
+    // row c - 1 read; ring row c + 3; rhs row c - 1 written; metric row c + 3),
+    // clamped or sent to a ghost cell where a step has nothing to do, so the
+    // wait for a ring row can leave everything issued after it in flight
+    constexpr int NMET = 1 + (CURVED ? 7 + (SHIFT ? 3 : 0) : 0);
+    const long odummy = rowb + p.g[0] - 1;               // an x ghost of rhs: written, never read
     R PLc[NF], Fprev[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) { PLc[f] = R(0); Fprev[f] = R(0); }
     double Jprev = 0.0;
+    // everything of the first window has landed before the loop: on both ways
+    // into the loop head the wait-count pass then sees the same loads pending
+    wait_ring();
 #pragma unroll 1
     for (int c = c0 - 1; c <= c1; ++c) {
-        const bool more = c < c1;
-        // metric and sigma of row c + 3, in flight during the step
-
+        const int cnext = min(c + 3, nD + 2);           // row c + 3, clamped inside the padding
         const bool fin = c - 1 >= c0;                   // rhs of c - 1 is finished this step
         const long om = base + (long)(c - 1 + gD) * s;
-        double acc[NF];
-        if (fin) {
+        double acc[NF], sacc[NF];
 #pragma unroll
-            for (int f = 0; f < NF; ++f) acc[f] = rhs[f * Np + om];
-        }
+        for (int f = 0; f < NF; ++f) acc[f] = rhs[f * Np + om];
+        // the sources go to their own sum: acc is first used at the store,
+        // so its loads have the whole step to land
+#pragma unroll
+        for (int f = 0; f < NF; ++f) sacc[f] = 0.0;
         if (fin && CURVED) {
             // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
             Geo<double> ms;
@@ -490,12 +501,9 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
 #pragma unroll
             for (int f = 0; f < NF; ++f) Pm[f] = ringP(c - 1, f);
             prim2con(ms, p.G, Pm, Um);
-            sources_dir<D>(p, ms, da, db, dg, Pm, Um, acc);
+            sources_dir<D>(p, ms, da, db, dg, Pm, Um, sacc);
         }
         __builtin_amdgcn_sched_barrier(0);
-        // the first step reads ring row c0 - 1 before its wait below: its
-        // load (issued just before the loop) must have landed first
-        if (c == c0 - 1) wait_ring();
         // current of c (metric and sigma row c: window 3)
         double Jc;
         {
@@ -514,8 +522,9 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             current(mc, Pc, ws[3], J);
             Jc = J[D];
         }
-        // ring row c + 2 (requested last step) must have landed
-        wait_ring();
+        // ring row c + 2 (requested last step) must have landed; issued after
+        // it: rhs row c - 2 written, metric row c + 2 and rhs row c - 1 read
+        wait_vm<NF + NMET + NF>();
         // reconstruction of c
         R fm[NF], fp[NF];
 #pragma unroll
@@ -529,8 +538,9 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         // row c - 2 is consumed: request row c + 3 into its slot
         __builtin_amdgcn_sched_barrier(0);
         asm volatile("" ::: "memory");
-        if (more) load_ring(c + 3);
-        if (c >= c0) {
+        load_ring(cnext);
+        {
+            // (the first step's face is not needed: computed, and stored to the ghost cell)
             // face c - 1/2: metric at the face from rows c-2 .. c+1 (window 1..4)
             Geo<R> m;
             if (CURVED) {
@@ -554,35 +564,34 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                 for (int f = 0; f < NF; ++f) PR[f] = R(ringP(c, f));
             R Fh[NF];
             face_flux<D>(p, m, PLc, PR, R(0.5 * (Jprev + Jc)), Fh);
-            if (fin && valid) {
+            // rhs row c - 1 (read at the top of the step) has landed once no more
+            // than the ring row c + 3 is in flight behind it
+            wait_vm<NF / 2>();
+            const long os = (fin && valid) ? om : odummy + (long)(c - 1 + gD) * s;
 #pragma unroll
-                for (int f = 0; f < NF; ++f) rhs[f * Np + om] = acc[f] + double(-(Fh[f] - Fprev[f]) * ih);
-            }
+            for (int f = 0; f < NF; ++f) rhs[f * Np + os] = acc[f] + (sacc[f] + double(-(Fh[f] - Fprev[f]) * ih));
 #pragma unroll
             for (int f = 0; f < NF; ++f) Fprev[f] = Fh[f];
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) PLc[f] = fp[f];
         Jprev = Jc;
-        // advance the register window by one row
-        if (more) {
-            double an = 0.0, bn[3] = {0.0, 0.0, 0.0}, gn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, sn = 0.0;
-            load_metric(c + 3, an, bn, gn, sn);
+        // advance the register window by one row, then load row c + 3 straight
+        // into its last place (a copy of a register still being loaded would
+        // make the step wait for that load, and so for all issued before it)
 #pragma unroll
-            for (int k = 0; k < 5; ++k) {
-                ws[k] = ws[k + 1];
-                if (CURVED) {
-                    wa[k] = wa[k + 1];
-                    if (SHIFT)
-                        for (int a = 0; a < 3; ++a) wb[SHIFT ? k : 0][a] = wb[SHIFT ? k + 1 : 0][a];
-                    for (int a = 0; a < 6; ++a) wg[k][a] = wg[k + 1][a];
-                }
+        for (int k = 0; k < 5; ++k) {
+            ws[k] = ws[k + 1];
+            if (CURVED) {
+                wa[k] = wa[k + 1];
+                if (SHIFT)
+                    for (int a = 0; a < 3; ++a) wb[SHIFT ? k : 0][a] = wb[SHIFT ? k + 1 : 0][a];
+                for (int a = 0; a < 6; ++a) wg[k][a] = wg[k + 1][a];
             }
-            ws[5] = sn;
-            wa[5] = an;
-            if (SHIFT)
-                for (int a = 0; a < 3; ++a) wb[SHIFT ? 5 : 0][a] = bn[a];
-            for (int a = 0; a < 6; ++a) wg[5][a] = gn[a];
+        }
+        {
+            double bdummy[3];
+            load_metric(cnext, wa[5], SHIFT ? wb[SHIFT ? 5 : 0] : bdummy, wg[5], ws[5]);
         }
     }
     // no ring load may be in flight when the wave ends

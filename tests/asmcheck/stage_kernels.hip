@@ -1,4 +1,5 @@
-// Instantiates every stage kernel and the FP64 x-flux kernels so that their
+// Instantiates every stage kernel, the FP64 x-flux kernels and y/z window
+// kernels so that their
 // gfx950 assembly can be checked
 // (tests/test_stage_waits.py); never linked into the library.
 #include <hip/hip_runtime.h>
@@ -9,6 +10,15 @@ template <int S, bool C, bool K> void inst(const Params& p, double* a, unsigned 
 }
 template <int RC, bool C> void inst_x(const Params& p, double* a) {
     k_flux_p<0, RC, C, double, false><<<8, 256>>>(p, a, a, a, 1, 1L);
+}
+template <int D, int RC, bool C, class R, bool SH> void inst_w(const Params& p, double* a) {
+    k_flux_w<D, RC, C, R, SH><<<8, 64>>>(p, a, a, a, 32, 1, 1);
+}
+void all_w(const Params& p, double* a) {
+    inst_w<1, 2, true, double, false>(p, a); inst_w<2, 2, true, double, false>(p, a);
+    inst_w<1, 1, true, double, false>(p, a); inst_w<2, 0, false, double, false>(p, a);
+    inst_w<1, 2, true, float, false>(p, a); inst_w<2, 2, true, float, false>(p, a);
+    inst_w<1, 2, true, double, true>(p, a); inst_w<2, 1, true, float, true>(p, a);
 }
 void all(const Params& p, double* a, unsigned long long* c, int* s) {
     inst_x<0, false>(p, a); inst_x<1, false>(p, a); inst_x<2, false>(p, a);

@@ -1,7 +1,8 @@
 """The stage kernels load the next chunk into LDS, the FP64 x-flux kernels
 the next segment into registers, and both then wait with s_waitcnt vmcnt(N),
 N = the stores of the current chunk or segment, so that those stores stay in
-flight.  That wait is only safe if every path from the last load into
+flight; the y/z window kernels wait for a ring row with vmcnt(36) (39 with a
+shift) and for the rhs row they read with vmcnt(7).  That wait is only safe if every path from the last load into
 LDS to the wait issues at least N vector-memory instructions (vmcnt counts
 them in order).  Compiles the kernels for gfx950 and checks it on the
 control-flow graph of their assembly (no device needed)."""
@@ -53,3 +54,30 @@ def test_kernel_waits_cover_their_loads(asm, kind, count, load):
             assert lo >= n, (name, n, lo)
             checked += 1
         assert checked >= 1, name
+
+
+def test_window_kernel_waits_cover_their_loads(asm):
+    ks = {k: v for k, v in asm.items() if "k_flux_w" in k}
+    assert len(ks) == 8
+    for name, L in ks.items():
+        m = re.search(r"k_flux_wILi(\d)ELi(\d)ELb(\d)E([df])Lb(\d)E", name)
+        curved, shift = m.group(3) == "1", m.group(5) == "1"
+        n_ring = 14 + 1 + ((7 + (3 if shift else 0)) if curved else 0) + 14
+        dma = [i for i, l in enumerate(L) if "global_load_lds_dwordx4" in l]
+        heads = [i for i, l in enumerate(L) if "Loop Header" in l and i < dma[-1]]
+        assert dma and heads, name
+        # ring rows: every path from the loop's last ring load to the ring wait
+        ring_waits = [i for i, l in enumerate(L) if re.search(rf"s_waitcnt vmcnt\({n_ring}\)", l)]
+        assert ring_waits, (name, n_ring)
+        for w in ring_waits:
+            lo, hi = path_counts(L, dma[-1] + 1, w)
+            print(f"{name[:44]}: vmcnt({n_ring}) after the ring load: {lo}..{hi}")
+            assert lo is not None and lo >= n_ring, (name, lo)
+        # rhs row: the 14 loads after the loop head, then the wait before the stores
+        rhs = [i for i, l in enumerate(L) if "global_load_dwordx2" in l and i > heads[-1]][:14]
+        rhs_waits = [i for i, l in enumerate(L) if "s_waitcnt vmcnt(7)" in l and i > rhs[-1]]
+        assert len(rhs) == 14 and rhs_waits, name
+        for w in rhs_waits:
+            lo, hi = path_counts(L, rhs[-1] + 1, w)
+            print(f"{name[:44]}: vmcnt(7) after the rhs loads: {lo}..{hi}")
+            assert lo is not None and lo >= 7, (name, lo)
