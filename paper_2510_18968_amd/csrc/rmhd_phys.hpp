@@ -560,13 +560,54 @@ __device__ __forceinline__ void lu4_solve(const double A[4][4], const int* piv, 
     }
 }
 
+// inverse of a 4x4 matrix by its adjugate over the determinant (Laplace
+// expansion in the 2x2 minors of rows 0-1 and rows 2-3): no pivot search, so
+// no data-dependent register indexing; false if the determinant is 0 or not
+// finite.  (The forward recovery only needs an approximate inverse for its
+// chord steps; the adjoint keeps the pivoted LU.)
+__device__ __forceinline__ bool inv4(const double A[4][4], double X[4][4]) {
+    const double s0 = A[0][0] * A[1][1] - A[1][0] * A[0][1];
+    const double s1 = A[0][0] * A[1][2] - A[1][0] * A[0][2];
+    const double s2 = A[0][0] * A[1][3] - A[1][0] * A[0][3];
+    const double s3 = A[0][1] * A[1][2] - A[1][1] * A[0][2];
+    const double s4 = A[0][1] * A[1][3] - A[1][1] * A[0][3];
+    const double s5 = A[0][2] * A[1][3] - A[1][2] * A[0][3];
+    const double c5 = A[2][2] * A[3][3] - A[3][2] * A[2][3];
+    const double c4 = A[2][1] * A[3][3] - A[3][1] * A[2][3];
+    const double c3 = A[2][1] * A[3][2] - A[3][1] * A[2][2];
+    const double c2 = A[2][0] * A[3][3] - A[3][0] * A[2][3];
+    const double c1 = A[2][0] * A[3][2] - A[3][0] * A[2][2];
+    const double c0 = A[2][0] * A[3][1] - A[3][0] * A[2][1];
+    const double det = s0 * c5 - s1 * c4 + s2 * c3 + s3 * c2 - s4 * c1 + s5 * c0;
+    if (!(fabs(det) > 0.0) || !isfinite(det)) return false;
+    const double id = 1.0 / det;
+    X[0][0] = (A[1][1] * c5 - A[1][2] * c4 + A[1][3] * c3) * id;
+    X[0][1] = (-A[0][1] * c5 + A[0][2] * c4 - A[0][3] * c3) * id;
+    X[0][2] = (A[3][1] * s5 - A[3][2] * s4 + A[3][3] * s3) * id;
+    X[0][3] = (-A[2][1] * s5 + A[2][2] * s4 - A[2][3] * s3) * id;
+    X[1][0] = (-A[1][0] * c5 + A[1][2] * c2 - A[1][3] * c1) * id;
+    X[1][1] = (A[0][0] * c5 - A[0][2] * c2 + A[0][3] * c1) * id;
+    X[1][2] = (-A[3][0] * s5 + A[3][2] * s2 - A[3][3] * s1) * id;
+    X[1][3] = (A[2][0] * s5 - A[2][2] * s2 + A[2][3] * s1) * id;
+    X[2][0] = (A[1][0] * c4 - A[1][1] * c2 + A[1][3] * c0) * id;
+    X[2][1] = (-A[0][0] * c4 + A[0][1] * c2 - A[0][3] * c0) * id;
+    X[2][2] = (A[3][0] * s4 - A[3][1] * s2 + A[3][3] * s0) * id;
+    X[2][3] = (-A[2][0] * s4 + A[2][1] * s2 - A[2][3] * s0) * id;
+    X[3][0] = (-A[1][0] * c3 + A[1][1] * c1 - A[1][2] * c0) * id;
+    X[3][1] = (A[0][0] * c3 - A[0][1] * c1 + A[0][2] * c0) * id;
+    X[3][2] = (-A[3][0] * s3 + A[3][1] * s1 - A[3][2] * s0) * id;
+    X[3][3] = (A[2][0] * s3 - A[2][1] * s1 + A[2][2] * s0) * id;
+    return true;
+}
+
 enum : int { ST_OK = 0, ST_WARN = 1, ST_NOCONV = -3, ST_UNPHYS = -4 };
 
-// residual r and LU of the exact Jacobian at x (the p column by hand, the v
-// columns by one 3-direction dual pass), factorised in place: JAC_OK, or JAC_UNPHYS (x
+// residual r and the inverse Ji of the exact Jacobian at x (the p column by
+// hand, the v columns by one 3-direction dual pass): JAC_OK, or JAC_UNPHYS (x
 // outside the physical domain), or JAC_SINGULAR
 enum { JAC_OK = 0, JAC_UNPHYS = 1, JAC_SINGULAR = 2 };
-__device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, double J[4][4], int* piv, double* r) {
+__device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, double Ji[4][4], double* r) {
+    double J[4][4];
     double c0[4];
     if (!rec_residual<double>(k, x, r, (double*)nullptr, c0)) return JAC_UNPHYS;
 #pragma unroll
@@ -581,7 +622,7 @@ __device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, dou
     for (int a = 0; a < 4; ++a)
 #pragma unroll
         for (int b = 0; b < 3; ++b) J[a][1 + b] = rd[a].d[b];
-    return lu4(J, piv) ? JAC_OK : JAC_SINGULAR;
+    return inv4(J, Ji) ? JAC_OK : JAC_SINGULAR;
 }
 
 // Stiff coupled solve: the root of the recovery map r(p, v) (the fixed point
@@ -592,8 +633,7 @@ __device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, dou
 // E out: densitised E at the root.
 __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, int maxit, int* iters) {
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
-    double r[4], J[4][4];
-    int piv[4];
+    double r[4], Ji[4][4];
     int it = 0, restart = 0;
     bool need = true, fresh = false;
     double last_rel = 1e300, prev_step = 1e300;
@@ -601,7 +641,7 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
     // the stage kernels within the instruction cache
     for (;;) {
         if (need) {
-            const int jst = rec_jacobian(k, x, J, piv, r);
+            const int jst = rec_jacobian(k, x, Ji, r);
             if (jst == JAC_UNPHYS && it == 0 && restart < 64) {
                 // guess outside the physical domain: restart at rest, then
                 // double the pressure until the state is physical
@@ -615,8 +655,9 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
             fresh = true;
         }
         if (++it > maxit) break;
-        double dx[4] = {-r[0], -r[1], -r[2], -r[3]};
-        lu4_solve(J, piv, dx);
+        double dx[4];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) dx[a] = -(Ji[a][0] * r[0] + Ji[a][1] * r[1] + Ji[a][2] * r[2] + Ji[a][3] * r[3]);
         const double m0 = rec_merit(r, x[0]);
         double t = 1.0, xt[4], rt[4];
         bool acc = false;
