@@ -212,6 +212,14 @@ int rmhd_recovery_stats_read(rmhd_ctx* ctx, int64_t* bins_out);
 int rmhd_timing(rmhd_ctx* ctx, int enable);
 int rmhd_timing_read(rmhd_ctx* ctx, double* ms_out, int64_t* launches_out);
 
+/* Make hip_stream (a hipStream_t; NULL = the default stream) the stream of
+ * every later call on this context.  Work already queued stays on the
+ * previous stream: order the two streams yourself.  (rmhd_step,
+ * rmhd_imex_stage, rmhd_step_adjoint and rmhd_prim2con only launch kernels
+ * when timing is off; the calls that return counters to the host
+ * synchronise the stream.) */
+int rmhd_set_stream(rmhd_ctx* ctx, void* hip_stream);
+
 /* Release the context (not the workspace). */
 int rmhd_destroy(rmhd_ctx* ctx);
 

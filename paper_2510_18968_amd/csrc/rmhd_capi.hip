@@ -643,6 +643,12 @@ int rmhd_timing_read(rmhd_ctx* c, double* ms_out, int64_t* launches_out) {
     return RMHD_OK;
 }
 
+int rmhd_set_stream(rmhd_ctx* c, void* hip_stream) {
+    if (!c) return fail(RMHD_EINVAL, "null context");
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    return RMHD_OK;
+}
+
 int rmhd_destroy(rmhd_ctx* c) {
     if (!c) return RMHD_OK;
     for (auto& v : c->ev)

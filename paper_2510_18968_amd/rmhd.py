@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "mixed": 1}
 SYMBOLS = ("rmhd_workspace_bytes", "rmhd_padded_extent", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
            "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
-           "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read")
+           "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read", "rmhd_set_stream")
 HIST_BINS = 32
 TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
 
@@ -57,6 +57,7 @@ def lib() -> C.CDLL:
         vp, gp = C.c_void_p, C.POINTER(GridDesc)
         sig = {
             "rmhd_workspace_bytes": (C.c_size_t, [gp]),
+            "rmhd_set_stream": (C.c_int, [vp, vp]),
             "rmhd_padded_extent": (C.c_int, [gp, C.POINTER(C.c_int32)]),
             "rmhd_init_grid": (C.c_int, [gp, vp, C.c_size_t, vp, C.POINTER(vp)]),
             "rmhd_set_metric": (C.c_int, [vp, vp, vp, vp, vp]),
@@ -167,6 +168,11 @@ class Grid:
 
     def _stream(self):
         return C.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+    def set_stream(self, stream=None):
+        """Launch later calls on `stream` (a torch stream; None: the current one)."""
+        st = torch.cuda.current_stream(self.device) if stream is None else stream
+        _check(lib().rmhd_set_stream(self._ctx, C.c_void_p(st.cuda_stream)), "rmhd_set_stream")
 
     def _ptr(self, t, nf=None, dtype=torch.float64):
         if t is None:

@@ -256,3 +256,4 @@ def test_rollout_checkpoint_interval_is_exact(R):
         out.append((host(gB), host(gs)))
     for gB, gs in out[1:]:
         assert np.array_equal(gB, out[0][0]) and np.array_equal(gs, out[0][1])
+

@@ -236,3 +236,29 @@ def test_failure_flags_and_counter(R, orc):
     stg = host(st)
     assert nf == nfo == 3
     assert np.array_equal(stg[I], sto[I])
+
+
+def test_set_stream_runs_on_the_given_stream(R):
+    """rmhd_set_stream: a step launched on a side stream (ordered after the
+    default stream's inputs, waited for before the read) gives the default
+    stream's result bit for bit."""
+    w = small_workloads()["blob20_weno5"]
+    g = R.grid_for(w)
+    g.set_metric(dev(w.metric))
+    sig = dev(w.sigma)
+    out = []
+    for side in (False, True):
+        P = dev(w.P)
+        U = g.prim2con(P)
+        if side:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            g.set_stream(s)
+            g.step(w.dt, sig, U, P)
+            torch.cuda.current_stream().wait_stream(s)
+            g.set_stream()
+        else:
+            g.step(w.dt, sig, U, P)
+        out.append((host(U), host(P)))
+    assert g.failures() == 0
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
