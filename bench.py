@@ -55,9 +55,9 @@ BYTES_PER_CELL = {
     # ghost layers only
     "ghost_fill": 0,
 }
-FLOPS_PER_CELL = {"flux_x": 3228.9, "flux_y": 2761.6, "flux_z": 2763.6, "update_stage2": 2318.3}
-TRAFFIC_BYTES_PER_CELL = {"flux_x": 185.1 + 116.6, "flux_y": 331.5 + 116.3, "flux_z": 329.9 + 115.0,
-                          "update_stage2": 508.2 + 265.0}
+FLOPS_PER_CELL = {"flux_x": 3232.6, "flux_y": 2813.1, "flux_z": 2815.2, "update_stage2": 2091.1}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 198.2 + 116.6, "flux_y": 334.0 + 112.1, "flux_z": 334.0 + 112.1,
+                          "update_stage2": 368.3 + 248.0}
 
 
 def parse():
