@@ -104,7 +104,10 @@ typedef struct {
  *                              out U_out = U^{n+1}, P_out = P^{n+1}
  * Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  For stage 3,
  * U_out may alias U_n and P_out may alias nothing else.  status is optional
- * ([Np] int32, interior cells written). */
+ * ([Np] int32, interior cells written).  A cell whose recovery fails (status
+ * < 0, counted by rmhd_failures) gets the primitives of its stage state at
+ * the guess's p and v with E = Ecal* (R = 0): a flagged non-solution, never
+ * a silently repaired one. */
 typedef struct {
     const double* U_n;
     const double* U_s;
