@@ -173,8 +173,15 @@ template <int D, int RECON, bool CURVED, class R, bool ACC> void flux_t(rmhd_ctx
 template <int D, int RECON, bool CURVED, class R> void flux_w(rmhd_ctx* c, const double* P, const double* sig) {
     const Params& p = c->p;
     constexpr int E = (D == 1) ? 2 : 1;
-    const int seglen = 32;
-    const int nxb = (p.n[0] + 63) / 64, nseg = (p.n[D] + seglen - 1) / seglen;
+    // segments as long as possible (each re-loads 3 halo rows at both ends
+    // and starts a window) while the columns x segments still give one wave
+    // per SIMD; at least 8 rows each
+    const int nxb = (p.n[0] + 63) / 64;
+    const long cols = (long)nxb * p.n[E];
+    const long want = 4L * c->persist_blocks;
+    const int nseg0 = (int)std::min<long>(std::max<long>(1, (want + cols - 1) / cols), (p.n[D] + 7) / 8);
+    const int seglen = (p.n[D] + nseg0 - 1) / nseg0;
+    const int nseg = (p.n[D] + seglen - 1) / seglen;
     const long waves = (long)nxb * p.n[E] * nseg;
     const long blocks = (waves + 7) / 8 * 8;          // one wave per block; multiple of 8 for the XCD renumbering
     if (CURVED && p.bet)
