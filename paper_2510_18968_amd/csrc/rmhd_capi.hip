@@ -159,8 +159,10 @@ template <int D, int RECON, bool CURVED, class R, bool ACC> void flux_t(rmhd_ctx
                                                                      const double* sig) {
     const Params& p = c->p;
     constexpr int E1 = (D == 0) ? 1 : 0, E2 = (D == 2) ? 1 : 2;
-    const int nseg = (p.n[D] + TSEG - 1) / TSEG;
-    const long items = (long)nseg * p.n[E1] * p.n[E2];
+    static_assert(D == 0, "the lane-per-cell sweep runs along x");
+    // the rows with their ghost cells as one sequence of 58-cell segments
+    const int nseg = 0;
+    const long items = ((long)(p.n[0] + 6) * p.n[E1] * p.n[E2] + TSEG - 1) / TSEG;
     const long need = (nblk(items, 4) + 7) / 8 * 8;   // multiple of 8 for the XCD renumbering
     if constexpr (std::is_same<R, float>::value) {
         k_flux_t<D, RECON, CURVED, R, ACC><<<need, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);

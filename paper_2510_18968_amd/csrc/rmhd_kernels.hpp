@@ -179,6 +179,12 @@ template <int D> struct FluxItem {
     long o;
 };
 
+// x sweep: the rows, each with its 3 ghost cells on both sides (n_x + 6
+// positions), are taken as one sequence; segment wid holds positions
+// 58 wid - 3 .. 58 wid + 60 of it.  Ghost cells are the halo at a row's ends,
+// so a segment may run across rows (a face between two rows is computed and
+// never used) and no lanes idle at a row's end.  it.c: interior x of the
+// lane's cell (outside 0..n_x-1 on ghost positions and past the end).
 template <int D>
 __device__ __forceinline__ FluxItem<D> flux_item(const Params& p, long wid, int nseg, int lane) {
     constexpr int E1 = (D == 0) ? 1 : 0, E2 = (D == 2) ? 1 : 2;
@@ -186,10 +192,18 @@ __device__ __forceinline__ FluxItem<D> flux_item(const Params& p, long wid, int 
     FluxItem<D> it;
     long a1, a2;
     if (D == 0) {
-        it.seg = (int)(wid % nseg);
-        const long r = wid / nseg;
+        const long W0 = p.n[0] + 6, V = W0 * n1 * p.n[E2];
+        const long v = wid * TSEG - 3 + lane;
+        const long vc = v < 0 ? 0 : (v < V ? v : V - 1);
+        const long r = vc / W0;
+        const int x = (int)(vc - r * W0) - 3;
         a1 = r % n1;
         a2 = r / n1;
+        it.seg = (int)wid;
+        it.c = v == vc ? x : -4;
+        it.cp = x + p.g[0];
+        it.o = (a1 + p.g[E1]) * p.st[E1] + (a2 + p.g[E2]) * p.st[E2] + (long)it.cp;
+        return it;
     } else {
         a1 = wid % n1;
         const long r = wid / n1;
@@ -228,7 +242,7 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
                                              int lane) {
     const long s = p.st[D], Np = p.Np, o = it.o;
     const int nD = p.n[D], gD = p.g[D];
-    const bool cell = lane >= 3 && lane < 3 + TSEG && it.c < nD;
+    const bool cell = lane >= 3 && lane < 3 + TSEG && it.c >= 0 && it.c < nD;
     double acc[NF];
     if (ACC) {
         // the read half of the read-modify-write, issued before the arithmetic
