@@ -89,6 +89,8 @@ bool check_desc(const rmhd_grid_desc* d, std::string& why) {
     long np = 1;
     for (int k = 0; k < 3; ++k) np *= d->n[k] + 2 * pad_lo(d, k);
     if (np > (1L << 36)) { why = "grid too large"; return false; }
+    // the x sweep indexes the rows with their ghost cells in 32 bits
+    if ((long)(d->n[0] + 6) * d->n[1] * d->n[2] + 64 > (1L << 31) - 1) { why = "grid too large"; return false; }
     return true;
 }
 

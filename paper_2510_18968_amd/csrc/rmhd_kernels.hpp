@@ -142,10 +142,12 @@ template <class R, class T> __device__ __forceinline__ R after(R v, T dep) {
 
 // Whole-wave lane shifts by DPP (VALU moves, no LDS round trip):
 // up<N>(v) on lane i is v of lane i - N, down<N>(v) is v of lane i + N; lanes
-// whose source is off the wave keep their own v (they carry no used result).
+// whose source is off the wave get 0 (they carry no used result).
 // Every lane of the wave must be active.
-__device__ __forceinline__ int dpp_up1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false); }
-__device__ __forceinline__ int dpp_dn1(int v) { return __builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false); }
+// (bound_ctrl: a lane whose source is off the wave reads 0, so no copy of
+// the old value has to be made first)
+__device__ __forceinline__ int dpp_up1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
+__device__ __forceinline__ int dpp_dn1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
 // (FP32 keeps the LDS-routed shuffle: a single DPP move per value leaves the
 // dependent shifts of a stencil back to back, which measured slower)
 template <bool UP> __device__ __forceinline__ float shift1(float v) { return UP ? __shfl_up(v, 1) : __shfl_down(v, 1); }
@@ -192,13 +194,15 @@ __device__ __forceinline__ FluxItem<D> flux_item(const Params& p, long wid, int 
     FluxItem<D> it;
     long a1, a2;
     if (D == 0) {
-        const long W0 = p.n[0] + 6, V = W0 * n1 * p.n[E2];
-        const long v = wid * TSEG - 3 + lane;
-        const long vc = v < 0 ? 0 : (v < V ? v : V - 1);
-        const long r = vc / W0;
-        const int x = (int)(vc - r * W0) - 3;
-        a1 = r % n1;
-        a2 = r / n1;
+        // 32-bit: the sequence has fewer than 2^31 positions (checked on the host)
+        const int W0 = p.n[0] + 6;
+        const int V = W0 * p.n[E1] * p.n[E2];
+        const int v = (int)wid * TSEG - 3 + lane;
+        const int vc = v < 0 ? 0 : (v < V ? v : V - 1);
+        const unsigned r = (unsigned)vc / (unsigned)W0;
+        const int x = vc - (int)r * W0 - 3;
+        a1 = r % (unsigned)p.n[E1];
+        a2 = r / (unsigned)p.n[E1];
         it.seg = (int)wid;
         it.c = v == vc ? x : -4;
         it.cp = x + p.g[0];
