@@ -982,10 +982,11 @@ struct Chunk {
     int x0;        // interior x of the chunk's first cell
 };
 __device__ __forceinline__ Chunk chunk_at(const Params& p, long q, int nsx) {
-    const long r = q / nsx;
-    const int seg = (int)(q - r * nsx);
-    const long j = r % p.n[1], k = r / p.n[1];
-    return Chunk{(k + p.g[2]) * p.st[2] + (j + p.g[1]) * p.st[1] + p.g[0], seg * 64};
+    // 32-bit: fewer than 2^31 chunks (the x-sweep bound on the descriptor covers it)
+    const unsigned uq = (unsigned)q, r = uq / (unsigned)nsx;
+    const int seg = (int)(uq - r * (unsigned)nsx);
+    const unsigned j = r % (unsigned)p.n[1], k = r / (unsigned)p.n[1];
+    return Chunk{((long)k + p.g[2]) * p.st[2] + ((long)j + p.g[1]) * p.st[1] + p.g[0], seg * 64};
 }
 
 // Ask for chunk c's streams straight into the wave's LDS buffer
