@@ -244,6 +244,91 @@ __global__ __launch_bounds__(128) void k_adj_cell(const Params p, const double* 
     if (sgb != 0.0) sb[o] += sgb;
 }
 
+// x direction, one lane per position of the sequence of rows with their
+// ghost cells (as the forward x sweep): a lane forms the whole gradient of its
+// own cell's reconstruction (recon_vjp, one reverse sweep) and cell c gathers
+// the components of the reconstructions c-2 .. c+2 from the neighbouring
+// lanes; 60 of a wave's 64 lanes gather.  The fallback and current parts are
+// those of k_adj_cell.
+constexpr int TSEGA = 60;
+template <int RECON, bool CURVED>
+__global__ __launch_bounds__(128) void k_adj_cell_x(const Params p, const double* __restrict__ P,
+                                                    const double* __restrict__ sig, const double* __restrict__ fb,
+                                                    double* __restrict__ Pb, double* __restrict__ sb, long nitems) {
+    const int lane = threadIdx.x & 63;
+    const long w = (long)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (w >= nitems) return;                                     // uniform per wave
+    const int n0 = p.n[0], gD = p.g[0];
+    const int W0 = n0 + 6;
+    const int V = W0 * p.n[1] * p.n[2];
+    const int v = (int)w * TSEGA - 2 + lane;
+    const int vc = v < 0 ? 0 : (v < V ? v : V - 1);
+    const unsigned r = (unsigned)vc / (unsigned)W0;
+    const int x = vc - (int)r * W0 - 3;                          // interior x: -3 .. n0 + 2
+    const unsigned j = r % (unsigned)p.n[1], k = r / (unsigned)p.n[1];
+    const long rowo = ((long)k + p.g[2]) * p.st[2] + ((long)j + p.g[1]) * p.st[1];
+    const long Np = p.Np;
+    const long o = rowo + gD + x;
+    const bool gather = lane >= 2 && lane < 2 + TSEGA && v == vc;
+    // the lane's cell m = c as a reconstruction: faces m - 1/2 (x >= 0) and m + 1/2 (x <= n0 - 1)
+    const bool isrec = x >= -1 && x <= n0;
+    const long oL = x >= 0 ? o - 1 : o;                          // left cell of face m - 1/2 (in range)
+    const int flR = x >= 0 ? (int)fb[29 * Np + oL] : 0;
+    const int flL = x <= n0 - 1 ? (int)fb[29 * Np + o] : 0;
+    const bool useR = isrec && x >= 0 && !(flR & 2);
+    const bool useL = isrec && x <= n0 - 1 && !(flL & 1);
+    double acc[NF];
+#pragma unroll 2
+    for (int f = 0; f < NF; ++f) {
+        double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (useR || useL) {
+            const double bm = useR ? fb[(NF + f) * Np + oL] : 0.0;
+            const double bp = useL ? fb[f * Np + o] : 0.0;
+            const double* a = P + f * Np + o;
+            const double st[5] = {a[-2], a[-1], a[0], a[1], a[2]};
+            recon_vjp<RECON>(st, bm, bp, g);
+        }
+        // cell c: g of c + 2 at 0, c + 1 at 1, c at 2, c - 1 at 3, c - 2 at 4
+        acc[f] = g[2] + (down<1>(g[1]) + down<2>(g[0])) + (up<1>(g[3]) + up<2>(g[4]));
+    }
+    if (!gather) return;
+    const long cpad = gD + x, lastD = gD + n0;
+    // first-order fallback states are the cell values themselves
+    if (cpad >= gD - 1 && cpad <= lastD - 1 && (flL & 1))
+        for (int f = 0; f < NF; ++f) acc[f] += fb[f * Np + o];
+    if (cpad >= gD && cpad <= lastD && (flR & 2))
+        for (int f = 0; f < NF; ++f) acc[f] += fb[(NF + f) * Np + oL];
+    // cell-centre current: J_face = (J_left + J_right)/2
+    double sgb = 0.0;
+    if (cpad >= gD - 1 && cpad <= lastD) {
+        double Jb = 0.0;
+        if (cpad >= gD) Jb += 0.5 * fb[28 * Np + oL];
+        if (cpad <= lastD - 1) Jb += 0.5 * fb[28 * Np + o];
+        if (Jb != 0.0) {
+            Geo<double> mc;
+            cell_geo_g<CURVED>(p, o, mc);
+            double Pc[NF];
+            for (int f = 0; f < NF; ++f) Pc[f] = P[f * Np + o];
+            const long os = o + (long)(bc_map(p, 0, (int)cpad) - cpad);
+            const double sg = sig[os];
+            const int dep[10] = {I_V, I_V + 1, I_V + 2, I_B, I_B + 1, I_B + 2, I_E, I_E + 1, I_E + 2, I_Q};
+            for (int a = 0; a < 10; ++a) {
+                D1 Pd[NF], J[3];
+                for (int f = 0; f < NF; ++f) Pd[f] = D1(Pc[f], f == dep[a] ? 1.0 : 0.0);
+                current(mc, Pd, D1(sg), J);
+                acc[dep[a]] += Jb * J[0].d;
+            }
+            D1 Pd[NF], J[3];
+            for (int f = 0; f < NF; ++f) Pd[f] = D1(Pc[f]);
+            current(mc, Pd, D1(sg, 1.0), J);
+            sgb = Jb * J[0].d;
+        }
+    }
+    for (int f = 0; f < NF; ++f)
+        if (acc[f] != 0.0) Pb[f * Np + o] += acc[f];
+    if (sgb != 0.0) sb[o] += sgb;
+}
+
 // --------------------------------------------------- ghost fill (reverse)
 // the ghost cells along d are copies of interior cells: add their adjoints to
 // the images and clear them (one thread owns one image row, deterministic);

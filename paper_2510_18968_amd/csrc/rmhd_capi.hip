@@ -302,7 +302,10 @@ template <bool CURVED, int RECON> int adj_L_t(rmhd_ctx* c, const double* P, cons
         if (d == 0) {
             k_adj_face<0, RECON, CURVED><<<nblk(nf, 128), 128, 0, c->stream>>>(p, P, sig, Lb, fb);
             LAUNCH_CHECK();
-            k_adj_cell<0, RECON, CURVED><<<nblk(nc, 128), 128, 0, c->stream>>>(p, P, sig, fb, Pb, sb);
+            const long items = ((long)(p.n[0] + 6) * p.n[1] * p.n[2] + TSEGA - 1) / TSEGA;   // 2 per block
+            k_adj_cell_x<RECON, CURVED><<<(unsigned)((items + 1) / 2), 128, 0, c->stream>>>(p, P, sig, fb, Pb, sb,
+                                                                                             items);
+            (void)nc;
         } else if (d == 1) {
             k_adj_face<1, RECON, CURVED><<<nblk(nf, 128), 128, 0, c->stream>>>(p, P, sig, Lb, fb);
             LAUNCH_CHECK();

@@ -347,6 +347,86 @@ template <int RECON, class R> __device__ __forceinline__ void recon(const R* s, 
     }
 }
 
+// Reverse of recon<RECON> at one cell: g[j] = bm dfm/ds[j] + bp dfp/ds[j]
+// (FP64).  Through the TVD limiters the derivative is that of the branch
+// taken, with the same comparisons as recon.
+template <int RECON> __device__ __forceinline__ void recon_vjp(const double* s, double bm, double bp, double* g) {
+    if constexpr (RECON == REC_WENO5) {
+        const double eps = 1e-6;
+        const double t0 = s[0] - 2.0 * s[1] + s[2], u0 = s[0] - 4.0 * s[1] + 3.0 * s[2];
+        const double t1 = s[1] - 2.0 * s[2] + s[3], u1 = s[1] - s[3];
+        const double t2 = s[2] - 2.0 * s[3] + s[4], u2 = 3.0 * s[2] - 4.0 * s[3] + s[4];
+        const double c13 = 13.0 / 12.0;
+        const double e0 = eps + (c13 * t0 * t0 + 0.25 * u0 * u0);
+        const double e1 = eps + (c13 * t1 * t1 + 0.25 * u1 * u1);
+        const double e2 = eps + (c13 * t2 * t2 + 0.25 * u2 * u2);
+        const double S0 = e0 * e0, S1 = e1 * e1, S2 = e2 * e2;
+        const double p12 = S1 * S2, p02 = S0 * S2, p01 = S0 * S1;
+        const double q0 = 2.0 * s[0] - 7.0 * s[1] + 11.0 * s[2];
+        const double q1 = -s[1] + 5.0 * s[2] + 2.0 * s[3];
+        const double q2 = 2.0 * s[2] + 5.0 * s[3] - s[4];
+        const double r0 = 2.0 * s[4] - 7.0 * s[3] + 11.0 * s[2];
+        const double r1 = -s[3] + 5.0 * s[2] + 2.0 * s[1];
+        const double r2 = 2.0 * s[2] + 5.0 * s[1] - s[0];
+        const double ap0 = 0.1 * p12, ap1 = 0.6 * p02, ap2 = 0.3 * p01;
+        const double am0 = 0.1 * p01, am1 = 0.6 * p02, am2 = 0.3 * p12;
+        // fp = Np / Dp, Dp = 6 (ap0 + ap1 + ap2); fm likewise
+        const double iDp = frcp(6.0 * (ap0 + ap1 + ap2)), iDm = frcp(6.0 * (am0 + am1 + am2));
+        const double fp = (ap0 * q0 + ap1 * q1 + ap2 * q2) * iDp;
+        const double fm = (am0 * r0 + am1 * r1 + am2 * r2) * iDm;
+        const double bNp = bp * iDp, bDp6 = -6.0 * bp * fp * iDp;
+        const double bNm = bm * iDm, bDm6 = -6.0 * bm * fm * iDm;
+        // adjoints of the weights, then of the products of squared indicators
+        const double bap0 = bNp * q0 + bDp6, bap1 = bNp * q1 + bDp6, bap2 = bNp * q2 + bDp6;
+        const double bam0 = bNm * r0 + bDm6, bam1 = bNm * r1 + bDm6, bam2 = bNm * r2 + bDm6;
+        const double bp12 = 0.1 * bap0 + 0.3 * bam2, bp02 = 0.6 * (bap1 + bam1), bp01 = 0.3 * bap2 + 0.1 * bam0;
+        const double bS0 = bp02 * S2 + bp01 * S1, bS1 = bp12 * S2 + bp01 * S0, bS2 = bp12 * S1 + bp02 * S0;
+        const double be0 = 2.0 * e0 * bS0, be1 = 2.0 * e1 * bS1, be2 = 2.0 * e2 * bS2;
+        const double bt0 = 2.0 * c13 * t0 * be0, bu0 = 0.5 * u0 * be0;
+        const double bt1 = 2.0 * c13 * t1 * be1, bu1 = 0.5 * u1 * be1;
+        const double bt2 = 2.0 * c13 * t2 * be2, bu2 = 0.5 * u2 * be2;
+        const double bq0 = bNp * ap0, bq1 = bNp * ap1, bq2 = bNp * ap2;
+        const double br0 = bNm * am0, br1 = bNm * am1, br2 = bNm * am2;
+        g[0] = bt0 + bu0 + 2.0 * bq0 - br2;
+        g[1] = -2.0 * bt0 - 4.0 * bu0 + bt1 + bu1 - 7.0 * bq0 - bq1 + 2.0 * br1 + 5.0 * br2;
+        g[2] = bt0 + 3.0 * bu0 - 2.0 * bt1 + bt2 + 3.0 * bu2 + 11.0 * bq0 + 5.0 * bq1 + 2.0 * bq2 + 11.0 * br0 +
+               5.0 * br1 + 2.0 * br2;
+        g[3] = bt1 - bu1 - 2.0 * bt2 - 4.0 * bu2 + 2.0 * bq1 + 5.0 * bq2 - 7.0 * br0 - br1;
+        g[4] = bt2 + bu2 - bq2 + 2.0 * br0;
+    } else {
+        // fm = s2 - sl/2, fp = s2 + sl/2, sl = limiter(dm, dp), dm = s2 - s1, dp = s3 - s2
+        const double dm = s[2] - s[1], dp = s[3] - s[2];
+        double gdm = 0.0, gdp = 0.0;                      // d sl / d dm, d sl / d dp
+        if constexpr (RECON == REC_MINMOD) {
+            if (!(dm * dp <= 0.0)) {
+                if (fabs(dm) < fabs(dp)) gdm = 1.0; else gdp = 1.0;
+            }
+        } else {   // MC2: minmod(2 dm, 2 dp, (dm + dp)/2) as recon takes it
+            if (!(dm * dp <= 0.0)) {
+                const double c = 0.5 * (dm + dp);
+                const double a = 2.0 * dm, b = 2.0 * dp;
+                int pick;                                 // 0: 2 dm, 1: 2 dp, 2: c
+                if (c > 0.0) {
+                    const int inner = a <= b ? 0 : 1;
+                    pick = (inner == 0 ? a : b) <= c ? inner : 2;
+                } else {
+                    const int inner = a >= b ? 0 : 1;
+                    pick = (inner == 0 ? a : b) >= c ? inner : 2;
+                }
+                if (pick == 0) gdm = 2.0;
+                else if (pick == 1) gdp = 2.0;
+                else { gdm = 0.5; gdp = 0.5; }
+            }
+        }
+        const double h = 0.5 * (bp - bm);
+        g[0] = 0.0;
+        g[1] = -h * gdm;
+        g[2] = (bm + bp) + h * (gdm - gdp);
+        g[3] = h * gdp;
+        g[4] = 0.0;
+    }
+}
+
 // ---------------------------------------------------------------- recovery
 // 3-direction dual number: value and derivatives with respect to (v^x, v^y,
 // v^z), the velocity columns of the recovery Jacobian in one pass
