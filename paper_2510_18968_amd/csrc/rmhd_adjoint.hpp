@@ -333,17 +333,21 @@ __global__ __launch_bounds__(128) void k_adj_cell_x(const Params p, const double
 // the ghost cells along d are copies of interior cells: add their adjoints to
 // the images and clear them (one thread owns one image row, deterministic);
 // the nf fields of a and then the one field of b
+// (one thread per image row, side and field; the layers of one row fold in
+// order, as the copies of a copy boundary share their image)
 __global__ void k_adj_fold(const Params p, double* __restrict__ a, int nf, double* __restrict__ b1, int d) {
     const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
     const long n1 = p.n[e1], n2 = p.n[e2];
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 2L * n1 * n2) return;
+    if (t >= 2L * n1 * n2 * (nf + 1)) return;
+    const int f = (int)(t / (2L * n1 * n2));
+    t -= (long)f * 2L * n1 * n2;
     const int side = (int)(t % 2);
     t /= 2;
     const long a1 = t % n1 + p.g[e1], a2 = t / n1 + p.g[e2];
     const long ob = a1 * p.st[e1] + a2 * p.st[e2];
     const int g = p.g[d], n = p.n[d];
-    for (int f = 0; f <= nf; ++f) {
+    {
         double* b = (f < nf ? a + f * p.Np : b1) + ob;
         for (int l = 0; l < p.ng; ++l) {
             const int c = side ? n + g + l : g - p.ng + l;

@@ -146,7 +146,7 @@ int ghost_fill(rmhd_ctx* c, double* a, int nf) {
     for (int d = 0; d < 3; ++d) {
         if (!is_active(p, d)) continue;
         const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
-        const long tot = 2L * p.ng * p.n[e1] * p.n[e2];
+        const long tot = 2L * p.ng * p.n[e1] * p.n[e2] * nf;
         Timed t(c, T_GHOST);
         k_ghost<<<nblk(tot, 256), 256, 0, c->stream>>>(p, a, nf, d);
         LAUNCH_CHECK();
@@ -320,7 +320,7 @@ template <bool CURVED, int RECON> int adj_L_t(rmhd_ctx* c, const double* P, cons
     for (int d = 0; d < 3; ++d) {
         if (!is_active(p, d)) continue;
         const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
-        const long nt = 2L * p.n[e1] * p.n[e2];
+        const long nt = 2L * p.n[e1] * p.n[e2] * (NF + 1);
         k_adj_fold<<<nblk(nt, 256), 256, 0, c->stream>>>(p, Pb, NF, sb, d);
         LAUNCH_CHECK();
     }

@@ -628,12 +628,15 @@ __global__ void k_any_nonzero(const double* __restrict__ a, long n, unsigned lon
 // ---------------------------------------------------------------- ghost fill
 // faces only: the ng ghost layers next to the interior along each active d,
 // interior extents elsewhere
+// (one thread per ghost cell and field: the copies are independent)
 __global__ void k_ghost(const Params p, double* __restrict__ a, int nf, int d) {
     const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
     const long n1 = p.n[e1], n2 = p.n[e2];
     const long tot = 2L * p.ng * n1 * n2;
     long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= tot) return;
+    if (t >= tot * nf) return;
+    const int f = (int)(t / tot);
+    t -= (long)f * tot;
     const int a1 = (int)(t % n1) + p.g[e1];
     t /= n1;
     const int a2 = (int)(t % n2) + p.g[e2];
@@ -643,7 +646,7 @@ __global__ void k_ghost(const Params p, double* __restrict__ a, int nf, int d) {
     const int src = bc_map(p, d, c);
     const long ob = (long)a1 * p.st[e1] + (long)a2 * p.st[e2];
     const long od = ob + (long)c * p.st[d], os = ob + (long)src * p.st[d];
-    for (int f = 0; f < nf; ++f) a[f * p.Np + od] = a[f * p.Np + os];
+    a[f * p.Np + od] = a[f * p.Np + os];
 }
 
 // ------------------------------------------------------------- interior map
