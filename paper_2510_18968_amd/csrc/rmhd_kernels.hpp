@@ -148,9 +148,10 @@ template <class R, class T> __device__ __forceinline__ R after(R v, T dep) {
 // the old value has to be made first)
 __device__ __forceinline__ int dpp_up1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x138, 0xf, 0xf, true); }
 __device__ __forceinline__ int dpp_dn1(int v) { return __builtin_amdgcn_mov_dpp(v, 0x130, 0xf, 0xf, true); }
-// (FP32 keeps the LDS-routed shuffle: a single DPP move per value leaves the
-// dependent shifts of a stencil back to back, which measured slower)
-template <bool UP> __device__ __forceinline__ float shift1(float v) { return UP ? __shfl_up(v, 1) : __shfl_down(v, 1); }
+template <bool UP> __device__ __forceinline__ float shift1(float v) {
+    const int b = __float_as_int(v);
+    return __int_as_float(UP ? dpp_up1(b) : dpp_dn1(b));
+}
 template <bool UP> __device__ __forceinline__ double shift1(double v) {
     const int lo = __double2loint(v), hi = __double2hiint(v);
     return __hiloint2double(UP ? dpp_up1(hi) : dpp_dn1(hi), UP ? dpp_up1(lo) : dpp_dn1(lo));
