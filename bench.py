@@ -55,8 +55,8 @@ BYTES_PER_CELL = {
     # ghost layers only
     "ghost_fill": 0,
 }
-FLOPS_PER_CELL = {"flux_x": 3232.6, "flux_y": 2813.1, "flux_z": 2815.2, "update_stage2": 2091.1}
-TRAFFIC_BYTES_PER_CELL = {"flux_x": 198.2 + 116.6, "flux_y": 334.0 + 112.1, "flux_z": 334.0 + 112.1,
+FLOPS_PER_CELL = {"flux_x": 2920.5, "flux_y": 2687.0, "flux_z": 2689.0, "update_stage2": 2091.1}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 201.8 + 120.0, "flux_y": 292.9 + 112.0, "flux_z": 292.9 + 112.0,
                           "update_stage2": 368.3 + 248.0}
 
 
