@@ -396,8 +396,9 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
 // is loaded once, straight from HBM into a ring of the last five rows in LDS
 // (global_load_lds_dwordx4: lane m brings two consecutive doubles of one of
 // two fields, so one instruction fills two 64-wide field rows; 35.8 KB per
-// wave); the metric and sigma rows of the window (c-3 .. c+2) stay in
-// registers.  Step c: rhs row c-1 is read, its sources are formed
+// wave); the metric and sigma rows c-3 .. c+1 stay in registers, and row
+// c+2, which step c does not use, waits in an LDS staging row, loaded the
+// same way one step ahead.  Step c: rhs row c-1 is read, its sources are formed
 // (derivatives from rows c-3..c+1), the current and the reconstruction of c
 // are taken; then row c+3 is requested into the ring slot that row c-2 has
 // just left, and while it arrives the face c-1/2 is computed and rhs row c-1
@@ -420,7 +421,13 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                                                const double* __restrict__ sig, double* __restrict__ rhs,
                                                int seglen, int nxb, int nseg) {
     constexpr int E = (D == 1) ? 2 : 1;                 // the other transverse dimension
-    __shared__ double ring[WRING * NF * 64];
+    // staging streams: sigma; alpha, gamma_ij (curved); beta^i (shift); an even count
+    constexpr int NMS = CURVED ? (SHIFT ? 12 : 8) : 2;
+    // one LDS object for the ring and the staging row: with two objects
+    // filled by direct loads the wait-count pass makes every ring read wait
+    // for all outstanding memory operations
+    __shared__ double ring[WRING * NF * 64 + NMS * 64];
+    double* const mst = ring + WRING * NF * 64;
     const int lane = threadIdx.x;
     const long wid = xcd_block();
     if (wid >= (long)nxb * p.n[E] * nseg) return;      // uniform per wave
@@ -451,8 +458,42 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                                              (__attribute__((address_space(3))) void*)(dst + f * 64), 16, 0, 0);
     };
 
-    // metric and sigma window, index k <-> row c - 3 + k
-    double wa[6], wb[SHIFT ? 6 : 1][3], wg[6][6], ws[6];
+    // metric and sigma window, index k <-> row c - 3 + k (k = 0..4).  Row c + 2
+    // is loaded one step ahead into the LDS staging row (same lane layout as
+    // the ring) and enters the window at the end of the next step, after the
+    // wait that covers it.  (Loaded into registers, the row would be copied
+    // into the window's registers right after its loads were issued, and the
+    // copy would wait for every memory operation issued before it.)
+    double wa[5], wb[SHIFT ? 5 : 1][3], wg[5][6], ws[5];
+    auto load_stage = [&](int c) {
+        const long ro = rowb + (long)(c + gD) * s + xpair;
+        const long rs = rowb + (long)bc_map(p, D, c + gD) * s + xpair;
+        auto addr = [&](int k) -> unsigned long long {
+            const double* b = (!CURVED || k == 0) ? sig + rs
+                            : k == 1 ? p.alp + ro
+                            : k < 8 ? p.gam + (long)(k - 2) * Np + ro
+                                    : p.bet + (long)min(k - 8, 2) * Np + ro;
+            return (unsigned long long)b;
+        };
+#pragma unroll
+        for (int q = 0; q < NMS / 2; ++q) {
+            // the lane's stream as an integer select (see the stage kernels)
+            const unsigned long long a = addr(2 * q), b = addr(2 * q + 1);
+            __builtin_amdgcn_global_load_lds((const void*)(fhalf ? b : a),
+                                             (__attribute__((address_space(3))) void*)(mst + 2 * q * 64), 16, 0, 0);
+        }
+    };
+    auto read_stage = [&](double& ar, double* br, double* gr, double& sr) {
+        sr = mst[lane];
+        if (CURVED) {
+            ar = mst[64 + lane];
+#pragma unroll
+            for (int a = 0; a < 6; ++a) gr[a] = mst[(2 + a) * 64 + lane];
+            if (SHIFT)
+#pragma unroll
+                for (int a = 0; a < 3; ++a) br[a] = mst[(8 + a) * 64 + lane];
+        }
+    };
     auto bw = [&](int k, int a) { return SHIFT ? wb[SHIFT ? k : 0][a] : 0.0; };
     auto load_metric = [&](int c, double& ar, double* br, double* gr, double& sr) {
         const long o = base + (long)(c + gD) * s;
@@ -466,9 +507,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         }
     };
     // window of the first step (c = c0 - 1): P rows c0-3 .. c0+1, metric rows
-    // c0-4 .. c0+1 (row c0-4 is outside the padding when c0 = 0 and unused)
+    // c0-4 .. c0 (row c0-4 is outside the padding when c0 = 0 and unused),
+    // staging row c0 + 1
     for (int c = c0 - 3; c <= c0 + 1; ++c) load_ring(c);
-    for (int k = 0; k < 6; ++k) {
+    load_stage(c0 + 1);
+    for (int k = 0; k < 5; ++k) {
         const int c = c0 - 4 + k;
         wa[k] = 0.0;
         ws[k] = 0.0;
@@ -480,10 +523,10 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     }
 
     // every step issues the same memory operations in the same order (rhs
-    // row c - 1 read; ring row c + 3; rhs row c - 1 written; metric row c + 3),
-    // clamped or sent to a ghost cell where a step has nothing to do, so the
-    // wait for a ring row can leave everything issued after it in flight
-    constexpr int NMET = 1 + (CURVED ? 7 + (SHIFT ? 3 : 0) : 0);
+    // row c - 1 read; ring row c + 3; rhs row c - 1 written; staging row
+    // c + 3), clamped or sent to a ghost cell where a step has nothing to do,
+    // so the wait for a ring row can leave everything issued after it in flight
+    constexpr int NMET = NMS / 2;
     const long odummy = rowb + p.g[0] - 1;               // an x ghost of rhs: written, never read
     R PLc[NF], Fprev[NF];
 #pragma unroll
@@ -595,11 +638,12 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
 #pragma unroll
         for (int f = 0; f < NF; ++f) PLc[f] = fp[f];
         Jprev = Jc;
-        // advance the register window by one row, then load row c + 3 straight
-        // into its last place (a copy of a register still being loaded would
-        // make the step wait for that load, and so for all issued before it)
+        // advance the window by one row: the staging row (row c + 2, asked
+        // for last step) has landed, since the wait before the stores above
+        // left only the ring row c + 3 in flight; once it is read, row c + 3
+        // is asked for in its place
 #pragma unroll
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < 4; ++k) {
             ws[k] = ws[k + 1];
             if (CURVED) {
                 wa[k] = wa[k + 1];
@@ -610,8 +654,10 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         }
         {
             double bdummy[3];
-            load_metric(cnext, wa[5], SHIFT ? wb[SHIFT ? 5 : 0] : bdummy, wg[5], ws[5]);
+            read_stage(wa[4], SHIFT ? wb[SHIFT ? 4 : 0] : bdummy, wg[4], ws[4]);
         }
+        wait_lgkm0();                                   // the staging row is read before it is refilled
+        load_stage(cnext);
     }
     // no ring load may be in flight when the wave ends
     wait_ring();

@@ -1,10 +1,12 @@
 """The stage kernels load the next chunk into LDS, the FP64 x-flux kernels
 the next segment into registers, and both then wait with s_waitcnt vmcnt(N),
 N = the stores of the current chunk or segment, so that those stores stay in
-flight; the y/z window kernels wait for a ring row with vmcnt(36) (39 with a
-shift) and for the rhs row they read with vmcnt(7).  That wait is only safe if every path from the last load into
-LDS to the wait issues at least N vector-memory instructions (vmcnt counts
-them in order).  Compiles the kernels for gfx950 and checks it on the
+flight; the y/z window kernels wait for a ring row with vmcnt(32) (34 with a
+shift, 29 on a flat metric) and for the rhs row they read with vmcnt(7).
+That wait is only safe if every path from the last load into LDS to the wait
+issues at least N vector-memory instructions (vmcnt counts them in order).
+Inside the loops of the x and window kernels no wait may be a full
+vmcnt(0), which would stall each step on every load in flight.  Compiles the kernels for gfx950 and checks it on the
 control-flow graph of their assembly (no device needed)."""
 import os
 import re
@@ -62,7 +64,8 @@ def test_window_kernel_waits_cover_their_loads(asm):
     for name, L in ks.items():
         m = re.search(r"k_flux_wILi(\d)ELi(\d)ELb(\d)E([df])Lb(\d)E", name)
         curved, shift = m.group(3) == "1", m.group(5) == "1"
-        n_ring = 14 + 1 + ((7 + (3 if shift else 0)) if curved else 0) + 14
+        # rhs stores, the staging row (sigma, alpha, gamma_ij, beta^i in pairs), rhs reads
+        n_ring = 14 + ((6 if shift else 4) if curved else 1) + 14
         dma = [i for i, l in enumerate(L) if "global_load_lds_dwordx4" in l]
         heads = [i for i, l in enumerate(L) if "Loop Header" in l and i < dma[-1]]
         assert dma and heads, name
@@ -81,3 +84,26 @@ def test_window_kernel_waits_cover_their_loads(asm):
             lo, hi = path_counts(L, rhs[-1] + 1, w)
             print(f"{name[:44]}: vmcnt(7) after the rhs loads: {lo}..{hi}")
             assert lo is not None and lo >= 7, (name, lo)
+
+
+def loop_full_waits(L):
+    """Lines in loop blocks (the compiler's "in Loop" label comments) that wait for every vector memory op."""
+    hits, inloop = [], False
+    for i, l in enumerate(L):
+        if re.match(r"^(\.LBB\S+:|; %bb\.\d+:)", l):
+            inloop = "Loop" in l
+        if inloop and re.search(r"s_waitcnt\s.*vmcnt\(0\)", l):
+            hits.append(i)
+    return hits
+
+
+def test_no_full_wait_inside_sweep_loops(asm):
+    ks = {k: v for k, v in asm.items() if "k_flux_w" in k or "k_flux_p" in k}
+    assert len(ks) == 14
+    checked = 0
+    for name, L in ks.items():
+        if any("scratch_" in l for l in L):
+            continue            # register spills are reloaded with full waits (the WENO5 FP64 shift variant)
+        assert not loop_full_waits(L), name
+        checked += 1
+    assert checked >= 12
