@@ -585,7 +585,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             Jc = J[D];
         }
         // ring row c + 2 (requested last step) must have landed; issued after
-        // it: rhs row c - 2 written, metric row c + 2 and rhs row c - 1 read
+        // it: rhs row c - 2 written, staging row c + 2 and rhs row c - 1 read
         wait_vm<NF + NMET + NF>();
         // reconstruction of c
         R fm[NF], fp[NF];
