@@ -210,7 +210,9 @@ int rmhd_recovery_stats_read(rmhd_ctx* ctx, int64_t* bins_out);
  * 4 stage-2 update + stiff recovery, 5 final update + recovery, 6 stage 1,
  * 7 other pointwise kernels.  rmhd_timing_read synchronises the stream,
  * writes the summed milliseconds and launch counts of each class since the
- * last read (arrays of RMHD_TIMING_CLASSES entries) and resets them. */
+ * last read (arrays of RMHD_TIMING_CLASSES entries) and resets them.  If an
+ * event could not be created or recorded since the last read, it resets the
+ * counts, writes nothing and returns RMHD_EHIP (the launches themselves ran). */
 #define RMHD_TIMING_CLASSES 8
 int rmhd_timing(rmhd_ctx* ctx, int enable);
 int rmhd_timing_read(rmhd_ctx* ctx, double* ms_out, int64_t* launches_out);

@@ -28,6 +28,7 @@ struct rmhd_ctx {
     long persist_blocks = 256;   // persistent flux grid: one 4-wave block per CU, multiple of 8
     // opt-in launch timing: event pairs per kernel class, reused after a read
     bool timing = false;
+    bool timing_err = false;   // an event could not be created or recorded since the last read
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[RMHD_TIMING_CLASSES];
     size_t used[RMHD_TIMING_CLASSES] = {};
 };
@@ -127,16 +128,22 @@ struct Timed {
         if (!c->timing) return;
         auto& v = c->ev[cls];
         if (c->used[cls] == v.size()) {
-            hipEvent_t a, b;
-            if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return;
+            hipEvent_t a = nullptr, b = nullptr;
+            if (hipEventCreate(&a) != hipSuccess) { c->timing_err = true; return; }
+            if (hipEventCreate(&b) != hipSuccess) {
+                (void)hipEventDestroy(a);
+                c->timing_err = true;
+                return;
+            }
             v.emplace_back(a, b);
         }
-        auto& pr = v[c->used[cls]++];
-        hipEventRecord(pr.first, c->stream);
+        auto& pr = v[c->used[cls]];
+        if (hipEventRecord(pr.first, c->stream) != hipSuccess) { c->timing_err = true; return; }
+        ++c->used[cls];
         stop = pr.second;
     }
     ~Timed() {
-        if (stop) hipEventRecord(stop, c->stream);
+        if (stop && hipEventRecord(stop, c->stream) != hipSuccess) c->timing_err = true;
     }
 };
 unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
@@ -643,6 +650,12 @@ int rmhd_timing(rmhd_ctx* c, int enable) {
 int rmhd_timing_read(rmhd_ctx* c, double* ms_out, int64_t* launches_out) {
     if (!c || !ms_out || !launches_out) return fail(RMHD_EINVAL, "null argument");
     HIP_TRY(hipStreamSynchronize(c->stream));
+    if (c->timing_err) {
+        // some launch went untimed or half-timed: report it rather than a partial sum
+        c->timing_err = false;
+        for (int k = 0; k < RMHD_TIMING_CLASSES; ++k) c->used[k] = 0;
+        return fail(RMHD_EHIP, "a timing event could not be created or recorded");
+    }
     for (int k = 0; k < RMHD_TIMING_CLASSES; ++k) {
         double tot = 0.0;
         for (size_t i = 0; i < c->used[k]; ++i) {
@@ -665,10 +678,11 @@ int rmhd_set_stream(rmhd_ctx* c, void* hip_stream) {
 
 int rmhd_destroy(rmhd_ctx* c) {
     if (!c) return RMHD_OK;
+    // teardown: a failure to destroy an event leaves nothing to recover
     for (auto& v : c->ev)
         for (auto& pr : v) {
-            hipEventDestroy(pr.first);
-            hipEventDestroy(pr.second);
+            (void)hipEventDestroy(pr.first);
+            (void)hipEventDestroy(pr.second);
         }
     delete c;
     return RMHD_OK;

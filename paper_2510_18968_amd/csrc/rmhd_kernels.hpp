@@ -100,6 +100,11 @@ __device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, cons
     for (int a = 0; a < NF; ++a) Fh[a] += cR * F[a] + cU * U[a];
 }
 
+// the metric-derivative sources of one direction (defined with the stage kernels)
+template <int d, class R>
+__device__ __forceinline__ void sources_dir(const Params& p, const Geo<double>& m, double da, const double* db,
+                                            const double* dg, const R* Pc, const R* Uc, R* S);
+
 // ----------------------------------------------------- fluxes, lanes along D
 // One wave per segment of TSEG cells along D; lane l holds the cell
 // seg*TSEG - 3 + l, so every lane loads its own 14 primitives and its metric
