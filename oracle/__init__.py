@@ -60,6 +60,7 @@ def lib():
             "orc_point_metric": (None, [dp, dp, dp]),
             "orc_point_flux": (None, [dp, C.c_double, dp, C.c_double, C.c_int, dp]),
             "orc_point_hlle": (None, [dp, C.c_double, dp, dp, C.c_double, C.c_int, C.c_int, dp]),
+            "orc_point_speeds": (None, [dp, C.c_int, C.c_int, dp, dp]),
             "orc_point_stiff": (None, [dp, dp, dp, dp, C.c_double, dp]),
             "orc_point_esolve": (None, [dp, dp, dp, dp, C.c_double, dp]),
             "orc_point_coupled": (C.c_int, [dp, C.c_double, dp, dp, C.c_double, C.c_double, dp, C.c_double,
@@ -158,6 +159,13 @@ def point_hlle(PL, PR, G, sigma, d, metric=None, mode=0):
                          _p(np.ascontiguousarray(PL, float)), _p(np.ascontiguousarray(PR, float)), sigma, d, mode,
                          _p(F))
     return F
+
+
+def point_speeds(metric, d, mode=0):
+    """characteristic speeds (lambda_+, lambda_-) of the HLLE flux along d"""
+    lp, lm = C.c_double(0), C.c_double(0)
+    lib().orc_point_speeds(_p(np.ascontiguousarray(metric, float)), d, mode, C.byref(lp), C.byref(lm))
+    return lp.value, lm.value
 
 
 def point_stiff(v, Ec, Bc, sigma, metric=None):

@@ -1205,6 +1205,13 @@ void orc_point_hlle(const double* mf, double G, const double* PL, const double* 
     char_speeds(m, d, mode, lp, lm);
     hlle(UL, UR, FL, FR, lp, lm, Fh);
 }
+void orc_point_speeds(const double* mf, int d, int mode, double* lp, double* lm) {
+    Metric<double> m;
+    double f[NM];
+    if (mf) std::memcpy(f, mf, sizeof f); else flat_fields(f);
+    metric_point(f, m);
+    char_speeds(m, d, mode, *lp, *lm);
+}
 void orc_point_stiff(const double* mf, const double* v, const double* Ec, const double* Bc, double sigma, double* R) {
     Metric<double> m;
     double f[NM];

@@ -1,0 +1,244 @@
+"""Pins of the oracle's shift and extrinsic-curvature terms (CPU only).
+
+Flat spacetime in a stationary but tilted slicing.  With Minkowski
+coordinates (T, X^i) and new coordinates t = T + h(x), x^i = X^i, the line
+element of Sec. II.A (eq. 3plus1_metric) has, in closed form,
+
+    gamma_ij = delta_ij - h_i h_j,   beta_i = h_i,   beta^i = alpha^2 h_i,
+    alpha = (1 - |grad h|^2)^(-1/2),  sqrt(gamma) = 1/alpha,
+
+(h_i = d_i h) and, since nothing depends on t, the extrinsic curvature in the
+sign convention of the paper's sources (the -alpha K Phi and
+alpha sqrt(gamma) S^ij K_ij terms of eq. GRRMHD_flux_form follow from
+d_t ln sqrt(gamma) = -alpha K + D_i beta^i) is
+
+    K_ij = (D_i beta_j + D_j beta_i) / (2 alpha) = alpha h_ij,
+
+because the Christoffel symbols of gamma_ij are Gamma^k_ij = -beta^k h_ij.
+
+Any static configuration of the Minkowski frame is then a time-independent
+solution in the new coordinates, so the continuum right-hand side of eq.
+GRRMHD_flux_form vanishes row by row, while every shift term (-beta^k U in
+each flux, d_i beta^j in the S, B and E sources) and every K term (tau, Phi,
+Psi sources) is nonzero.  The configuration used: fluid at rest in the
+Minkowski frame with uniform rho and B_flat, uniform charge q0 with the
+electrostatic field E_flat = q0 (X - Xc)/3 it sources, the pressure
+p = p0 + q0^2 |X - Xc|^2 / 6 that balances q0 E_flat, sigma = 0, and
+uniform cleaning scalars psi0, phi0 with kappa = 0 (with kappa = 0 they are
+4-scalars, so they stay uniform in any slicing).  Transformed exactly:
+
+    u^t = 1, u^i = 0  ->  W = alpha, v^i = alpha h_i,
+    Ecal = E_flat - h x B_flat,   Bcal = B_flat + h x E_flat,
+    Qcal = q0,  Psi = psi0/alpha,  Phi = phi0/alpha,
+
+(Ecal from Ecal^i = -F^{it}, Bcal^i = eta^{ijk} F_jk / 2 with alpha sqrt(gamma)
+= 1), so the undensitised primitives are E = alpha Ecal, B = alpha Bcal,
+q = alpha q0.  A second case keeps sigma > 0 with q0 = 0 and E_flat = 0:
+the fluid-frame electric field vanishes, so Ohm's law (eq. Ohm_law) gives no
+current and the state is again stationary.
+
+The oracle's discrete right-hand side must converge to zero at second order
+on all 14 rows.  Dropping or flipping the sign of any single shift or K term
+leaves an O(1) residual, which this test catches.
+"""
+import math
+
+import numpy as np
+import pytest
+
+# h(x) = sum_m a_m sin(k n_m . x + c_m): smooth, with every first and second
+# derivative (mixed ones included) nonzero somewhere
+_MODES = [
+    (0.034, (1.0, 0.0, 0.0), 0.3),
+    (0.026, (0.0, 1.0, 0.0), 1.1),
+    (0.022, (0.0, 0.0, 1.0), 2.0),
+    (0.019, (1.0, 1.0, 0.0), 0.7),
+    (0.015, (0.0, 1.0, -1.0), 2.9),
+    (0.015, (1.0, 0.0, 1.0), 4.1),
+]
+_K = 2.0 * math.pi
+
+
+def slicing_fields(x, y, z, modes=_MODES, dims=3):
+    """grad h and the Hessian of h at the points (x, y, z); modes with a
+    component along an inactive dimension are dropped"""
+    X = (x, y, z)
+    hi = [np.zeros_like(x) for _ in range(3)]
+    hij = [[np.zeros_like(x) for _ in range(3)] for _ in range(3)]
+    for a, n, c in modes:
+        if any(n[d] != 0.0 for d in range(dims, 3)):
+            continue
+        th = _K * (n[0] * X[0] + n[1] * X[1] + n[2] * X[2]) + c
+        cs, sn = np.cos(th), np.sin(th)
+        for i in range(3):
+            hi[i] = hi[i] + a * _K * n[i] * cs
+            for j in range(3):
+                hij[i][j] = hij[i][j] - a * _K * _K * n[i] * n[j] * sn
+    return np.array(hi), np.array(hij)
+
+
+def slicing_state(n, dims, q0, sig, psi0, phi0, B0=(0.31, -0.22, 0.17), rho0=1.0, p0=0.6):
+    """metric (16 fields) and primitives (14 fields) on the padded grid"""
+    dx = 1.0 / n
+    c = -0.5 + dx * (np.arange(-3, n + 3) + 0.5)
+    shape = [n + 6 if d < dims else 1 for d in range(3)]
+    ax = [c if d < dims else np.zeros(1) for d in range(3)]
+    Z, Y, Xg = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    hi, hij = slicing_fields(Xg, Y, Z, dims=dims)
+    h2 = (hi * hi).sum(0)
+    assert h2.max() < 0.4
+    alp = 1.0 / np.sqrt(1.0 - h2)
+    met = np.zeros((16,) + Xg.shape)
+    met[0] = alp
+    for i in range(3):
+        met[1 + i] = alp * alp * hi[i]
+    sym = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
+    for s, (i, j) in enumerate(sym):
+        met[4 + s] = (1.0 if i == j else 0.0) - hi[i] * hi[j]
+        met[10 + s] = alp * hij[i][j]
+    # Minkowski-frame fields: E_flat = q0 (X - Xc)/3 solves div E = q0
+    Xc = (0.07, -0.05, 0.03)
+    R = np.array([Xg - Xc[0], Y - Xc[1], Z - Xc[2]])
+    if dims < 3:
+        # fewer dimensions: the field of a uniform slab charge along the active ones
+        for d in range(dims, 3):
+            R[d] = 0.0
+    Ef = q0 * R / dims
+    Bf = np.array([np.full(Xg.shape, b) for b in B0])
+    Ecal = Ef - np.cross(hi, Bf, axis=0)
+    Bcal = Bf + np.cross(hi, Ef, axis=0)
+    P = np.zeros((14,) + Xg.shape)
+    P[0] = rho0
+    P[1] = p0 + q0 * q0 * (R * R).sum(0) / (2.0 * dims)
+    P[2:5] = alp * hi
+    P[5:8] = alp * Bcal
+    P[8:11] = alp * Ecal
+    P[11] = phi0
+    P[12] = psi0
+    P[13] = alp * q0
+    sigma = np.full(Xg.shape, sig)
+    return met, P, sigma, dx, shape
+
+
+def rhs_residual(orc, n, dims, recon, **kw):
+    met, P, sigma, dx, shape = slicing_state(n, dims, **kw)
+    active = (1 << dims) - 1
+    nn = [n if d < dims else 1 for d in range(3)]
+    g = orc.make_grid(nn, active, (dx,) * 3, (orc.BC_GIVEN,) * 3, 4.0 / 3.0, recon=recon, kappa=0.0,
+                      x0=tuple(-0.5 + 0.5 * dx if d < dims else 0.0 for d in range(3)))
+    L = orc.explicit_rhs(g, np.ascontiguousarray(P), np.ascontiguousarray(sigma), np.ascontiguousarray(met))
+    I = orc.interior(g)
+    U = orc.prim2con(g, np.ascontiguousarray(P), np.ascontiguousarray(met))
+    scale = np.abs(U[(slice(None),) + I]).reshape(14, -1).max(1)
+    # EM, cleaning and charge rows against the field scale (a component that
+    # vanishes in the continuum still carries truncation error)
+    scale[5:] = np.maximum(scale[5:], scale[5:11].max())
+    return np.abs(L[(slice(None),) + I]).reshape(14, -1).mean(1), scale
+
+
+CASES = {
+    "charged_sigma0": dict(q0=0.4, sig=0.0, psi0=0.2, phi0=-0.15),
+    "neutral_sigma100": dict(q0=0.0, sig=100.0, psi0=0.2, phi0=-0.15),
+}
+
+
+def slicing_failures(orc, case, dims):
+    """rows of the tilted-slicing right-hand side that do not converge to
+    zero at second order (empty when the pin holds)"""
+    kw = CASES[case]
+    sizes = (16, 32) if dims == 3 else (32, 64)
+    (e0, scale), (e1, _) = [rhs_residual(orc, n, dims, orc.REC_WENO5, **kw) for n in sizes]
+    bad = []
+    for f in range(14):
+        # a row that is zero in the continuum and in the discretisation
+        # (no charge: the charge row) carries round-off only
+        if e0[f] <= 1e-12 * scale[f] and e1[f] <= 1e-12 * scale[f]:
+            continue
+        rate = math.log2(e0[f] / e1[f]) if e1[f] > 0 else float("inf")
+        if not (rate >= 1.7 and e1[f] <= 1e-2 * scale[f]):
+            bad.append((f, e0[f] / scale[f], e1[f] / scale[f], rate))
+    return bad
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+@pytest.mark.parametrize("dims", [1, 2, 3])
+def test_tilted_slicing_rhs_vanishes(orc, case, dims):
+    """eq. GRRMHD_flux_form with shift and extrinsic curvature: the explicit
+    right-hand side of a static Minkowski configuration seen from a tilted
+    stationary slicing converges to zero at second order on every row."""
+    bad = slicing_failures(orc, case, dims)
+    assert not bad, (case, dims, bad)
+
+
+def test_tilted_slicing_terms_are_live(orc):
+    """The configuration exercises the terms the test above pins: the shift,
+    its derivatives, K and the fields they multiply are all O(1)."""
+    met, P, sigma, dx, shape = slicing_state(16, 3, **CASES["charged_sigma0"])
+    assert np.abs(met[1:4]).max() > 0.2            # beta^i
+    assert np.abs(met[10:16]).max() > 0.5          # K_ij
+    assert np.abs(P[8:11]).max() > 0.05            # E (Eulerian)
+    assert np.abs(P[13]).max() > 0.3               # q
+    assert np.abs(np.diff(met[1], axis=2)).max() / dx > 1.0   # d_x beta^x
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_coordinate_speeds_of_the_light_cone(orc, seed):
+    """speed_mode = 1 (alpha sqrt(gamma^dd) -+ beta^d): the coordinate speeds
+    lambda of a characteristic surface x^d - lambda t = const of the light
+    cone, i.e. the roots of g^{mu nu} xi_mu xi_nu = 0 for xi = (-lambda, e_d)
+    with the inverse 4-metric printed in Sec. II.A.  speed_mode = 0 is the
+    printed -beta^d/alpha +- sqrt(gamma^dd)."""
+    rng = np.random.default_rng(100 + seed)
+    A = rng.uniform(-0.3, 0.3, (3, 3))
+    gam = np.eye(3) + 0.5 * (A + A.T) + 0.3 * np.eye(3)
+    alp = rng.uniform(0.4, 1.5)
+    beta = rng.uniform(-0.4, 0.4, 3)
+    met = np.zeros(16)
+    met[0], met[1:4] = alp, beta
+    for s, (i, j) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        met[4 + s] = gam[i, j]
+    gi = np.linalg.inv(gam)
+    # g^{mu nu} of Sec. II.A
+    g4 = np.zeros((4, 4))
+    g4[0, 0] = -1.0 / alp ** 2
+    g4[0, 1:] = g4[1:, 0] = beta / alp ** 2
+    g4[1:, 1:] = gi - np.outer(beta, beta) / alp ** 2
+    for d in range(3):
+        # xi = (-lambda, e_d): g^00 lambda^2 - 2 g^0d lambda + g^dd = 0
+        roots = np.sort(np.roots([g4[0, 0], -2.0 * g4[0, 1 + d], g4[1 + d, 1 + d]]).real)
+        lp, lm = orc.point_speeds(met, d, mode=1)
+        assert abs(lp - roots[1]) <= 1e-14 * (1 + abs(roots[1])), (d, lp, roots)
+        assert abs(lm - roots[0]) <= 1e-14 * (1 + abs(roots[0])), (d, lm, roots)
+        lp0, lm0 = orc.point_speeds(met, d, mode=0)
+        s = math.sqrt(gi[d, d])
+        assert abs(lp0 - (s - beta[d] / alp)) <= 1e-14 and abs(lm0 - (-s - beta[d] / alp)) <= 1e-14
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_light_cone_speeds_bound_the_maxwell_characteristics(orc, seed):
+    """The EM rows of eq. GRRMHD_flux_form (Bcal, Ecal, Phi, Psi, at zero
+    current) are linear in (Bcal, Ecal, Phi, Psi); the eigenvalues of their
+    flux Jacobian along d are the characteristic speeds, and the largest and
+    smallest of them are the light-cone speeds of speed_mode = 1."""
+    rng = np.random.default_rng(200 + seed)
+    A = rng.uniform(-0.3, 0.3, (3, 3))
+    gam = np.eye(3) + 0.5 * (A + A.T) + 0.3 * np.eye(3)
+    met = np.zeros(16)
+    met[0] = rng.uniform(0.4, 1.5)
+    met[1:4] = rng.uniform(-0.4, 0.4, 3)
+    for s, (i, j) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        met[4 + s] = gam[i, j]
+    gi, sg = orc.point_metric(met)
+    base = np.zeros(14)
+    base[0], base[1] = 1.0, 1.0
+    rows = [5, 6, 7, 8, 9, 10, 11, 12]
+    for d in range(3):
+        J = np.zeros((8, 8))
+        F0 = orc.point_flux(base, 2.0, 0.0, d, met)
+        for c, f in enumerate(rows):
+            Pp = base.copy()
+            Pp[f] = 1.0 / sg     # unit step of the densitised variable
+            J[:, c] = (orc.point_flux(Pp, 2.0, 0.0, d, met)[rows] - F0[rows])
+        ev = np.sort(np.linalg.eigvals(J).real)
+        lp, lm = orc.point_speeds(met, d, mode=1)
+        assert abs(ev[-1] - lp) <= 1e-12 and abs(ev[0] - lm) <= 1e-12, (d, ev, lp, lm)
