@@ -175,7 +175,12 @@ size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc);
  * their local Jacobians, the stage combination of eq. IMEX3 exactly; limiter
  * kinks and first-order fallbacks take the derivative of the branch taken.
  * Ubar_n may alias Ubar_np1.  adj_ws: >= rmhd_adjoint_workspace_bytes bytes,
- * 256-byte aligned.  Returns RMHD_EINVAL for the mixed-precision form. */
+ * 256-byte aligned.  Returns RMHD_EINVAL for the mixed-precision form.  A
+ * cell whose recovery Jacobian is singular at the root has no implicit-
+ * function derivative: its multiplier is set to zero and the cell is counted
+ * by rmhd_failures() (as are failed recoveries of the recomputed forward
+ * stages), so a caller that finds a nonzero count must not trust the
+ * gradient. */
 int rmhd_step_adjoint(rmhd_ctx* ctx, double dt, const double* sigma, const double* U_n, const double* P_n,
                       const double* Ubar_np1, double* Ubar_n, double* sigma_bar, void* adj_ws, size_t adj_bytes);
 

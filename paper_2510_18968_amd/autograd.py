@@ -60,6 +60,10 @@ class RMHDRollout(torch.autograd.Function):
             for Un, Pn in reversed(states):
                 g.step_adjoint(dt, sig, Un, Pn, Ub, Ub, sbar)
         ctx.checkpoints = None
+        # failed recoveries in the recomputed forward steps or singular
+        # recovery Jacobians in the adjoint: the gradient is not trustworthy
+        if g.failures():
+            raise RuntimeError("recovery failures or singular recovery Jacobians in the backward rollout")
         return Ub, sbar, None, None, None, None, None
 
 

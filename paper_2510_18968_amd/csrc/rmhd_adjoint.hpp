@@ -38,8 +38,9 @@ __global__ void k_fill(double* a, long n, double v) {
 }
 
 // -------------------------------------------------------- final update (reverse)
-__global__ __launch_bounds__(256) void k_adj_final(const Params p, double dt, const double* __restrict__ Ub1,
-                                                   double* __restrict__ Ubn, double* __restrict__ Ub2,
+// Ub1 and Ubn may be the same array (in-place adjoint): no __restrict__ on them
+__global__ __launch_bounds__(256) void k_adj_final(const Params p, double dt, const double* Ub1,
+                                                   double* Ubn, double* __restrict__ Ub2,
                                                    double* __restrict__ Lb, double* __restrict__ R1b,
                                                    double* __restrict__ R2b) {
     long o;
@@ -418,7 +419,8 @@ __global__ __launch_bounds__(128) void k_adj_point(const Params p, double dt, co
                                                    const double* __restrict__ Ps, const double* __restrict__ Ubs,
                                                    const double* __restrict__ Pb, const double* __restrict__ Rb,
                                                    double* __restrict__ Ubn, double* __restrict__ Lb,
-                                                   double* __restrict__ R1b, double* __restrict__ sb) {
+                                                   double* __restrict__ R1b, double* __restrict__ sb,
+                                                   unsigned long long* __restrict__ nfail) {
     long o;
     if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
     const long Np = p.Np;
@@ -450,8 +452,14 @@ __global__ __launch_bounds__(128) void k_adj_point(const Params p, double dt, co
     }
     int piv[4];
     double lam[4] = {xb[0], xb[1], xb[2], xb[3]};
-    if (lu4(J, piv)) lu4_solve(J, piv, lam);
-    else lam[0] = lam[1] = lam[2] = lam[3] = 0.0;
+    if (lu4(J, piv)) {
+        lu4_solve(J, piv, lam);
+    } else {
+        // a singular Jacobian at the root has no implicit-function derivative:
+        // the cell is counted as failed (rmhd_failures), its lambda set to zero
+        lam[0] = lam[1] = lam[2] = lam[3] = 0.0;
+        atomicAdd(nfail, 1ull);
+    }
     double thb[NTH];
     for (int b = 0; b < NTH; ++b) {
         D1 xd[4], thd[NTH], rd[4], Om;

@@ -354,10 +354,10 @@ int adj_point(rmhd_ctx* c, double dt, const double* sig, const double* Us, const
     const long n = ncells(c->p);
     if (c->curved)
         k_adj_point<STAGE, true><<<nblk(n, 128), 128, 0, c->stream>>>(c->p, dt, sig, Us, Rs, Ps, Ubs, Pb, Rb, Ubn,
-                                                                      Lb, R1b, sb);
+                                                                      Lb, R1b, sb, c->counters);
     else
         k_adj_point<STAGE, false><<<nblk(n, 128), 128, 0, c->stream>>>(c->p, dt, sig, Us, Rs, Ps, Ubs, Pb, Rb, Ubn,
-                                                                       Lb, R1b, sb);
+                                                                       Lb, R1b, sb, c->counters);
     LAUNCH_CHECK();
     return RMHD_OK;
 }

@@ -2,13 +2,15 @@
 //
 // Data: float64 SoA over the padded grid (x fastest), one field per plane.
 // The flux divergence is split by direction:
-//   x: one wave64 per row segment of 62 cells; every lane reconstructs its
-//      own cell to both faces (shared WENO smoothness indicators), the right
-//      neighbour's left-face state and the left neighbour's face flux arrive
-//      by cross-lane shuffles, so each face flux is computed once;
-//   y, z: lanes run along x (coalesced loads) and each lane marches along the
-//      flux direction, carrying the previous face state and flux in
-//      registers.
+//   x: the rows with their ghost cells form one sequence, cut into segments
+//      of 58 positions; a wave64 holds one segment plus 3 halo lanes on each
+//      side, every lane reconstructs its own cell to both faces (shared WENO
+//      smoothness indicators), and the right neighbour's left-face state and
+//      the left neighbour's face flux arrive by DPP lane moves, so each face
+//      flux is computed once;
+//   y, z: lanes run along x (coalesced loads) and each wave marches a
+//      segment along the flux direction through a ring of the last five rows
+//      of P in LDS, carrying the previous face state and flux in registers.
 // The pointwise kernels add the non-stiff sources, assemble the IMEX stage
 // and run the stiff recovery, one cell per lane.
 #pragma once

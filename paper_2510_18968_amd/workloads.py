@@ -300,6 +300,171 @@ def sheet_batch(nprob=64, n=2048, seed=501, target_seed=502, cfl=0.25, steps=200
                     extra=dict(seed=seed, sigma_problem=sig, sigma_target=sig_t))
 
 
+# ------------------------------------------------- paper tests of Sec. IV
+def brio_wu(sigma0=1e6, n=400, cfl=0.25, t_end=0.4, sigma_exp=None) -> Workload:
+    """The shocktube of Sec. IV.A as printed: (rho, p, B^y) = (1, 1, 0.5) for
+    x < 0 and (0.125, 0.1, -0.5) for x > 0, v = B^x = B^z = E = 0, Gamma = 2,
+    minmod, copy boundaries, on [-0.5, 0.5] with Delta x = 1/n.  sigma_exp
+    (gamma of eq. sigma_evol) is recorded for the sigma(D) model; the static
+    sigma field is sigma0."""
+    dx = 1.0 / n
+    nn = (n, 1, 1)
+    x0 = -0.5 + 0.5 * dx
+    x, _, _ = _coords(nn, 1, (x0, 0.0, 0.0), (dx, 1.0, 1.0))
+    left = (x < 0.0)[None]
+    shape = (1, 1, n + 2 * NG)
+    P = np.zeros((14,) + shape)
+    P[0] = np.where(left, 1.0, 0.125)
+    P[1] = np.where(left, 1.0, 0.1)
+    P[6] = np.where(left, 0.5, -0.5)
+    sigma = np.full(shape, float(sigma0))
+    steps = int(round(t_end / (cfl * dx)))
+    return Workload(f"brio_wu_{n}", nn, 1, (dx, 1.0, 1.0), (x0, 0.0, 0.0), (1, 1, 1), 2.0, RECON["minmod"],
+                    t_end / steps, steps, P, sigma, None, extra=dict(sigma0=sigma0, sigma_exp=sigma_exp, cfl=cfl))
+
+
+def alfven_speed(rho, p, eta_A, B0, gamma_ad):
+    """eq. Alf_vel, with h the enthalpy density rho (1 + eps) + p of an ideal gas"""
+    h = rho + gamma_ad / (gamma_ad - 1.0) * p
+    a = 2.0 * B0 ** 2 / (h + B0 ** 2 * (1.0 + eta_A ** 2))
+    b = 2.0 * eta_A * B0 ** 2 / (h + B0 ** 2 * (1.0 + eta_A ** 2))
+    return math.sqrt(a / (1.0 + math.sqrt(1.0 - b * b)))
+
+
+def cp_alfven(n=200, cfl=0.25, sigma0=1e6, rho=1.0, p=1.0, eta_A=1.0, B0=1.1547, periods=1.0) -> Workload:
+    """The large-amplitude circularly polarised Alfven wave of Sec. IV.D
+    (eqs. Bi, vyvz, Alf_vel, E = -v x B): periodic x in [-0.5, 0.5], k = 2 pi,
+    Gamma = 2, MC2, uniform sigma; run for `periods` wave periods L/v_A."""
+    G = 2.0
+    vA = alfven_speed(rho, p, eta_A, B0, G)
+    dx = 1.0 / n
+    nn = (n, 1, 1)
+    x0 = -0.5 + 0.5 * dx
+    x = x0 + dx * np.arange(-NG, n + NG)
+    k = 2.0 * math.pi
+    shape = (1, 1, n + 2 * NG)
+    P = np.zeros((14,) + shape)
+    By, Bz = eta_A * B0 * np.cos(k * x), eta_A * B0 * np.sin(k * x)
+    P[0], P[1], P[5] = rho, p, B0
+    P[6, 0, 0], P[7, 0, 0] = By, Bz
+    P[3, 0, 0], P[4, 0, 0] = -vA / B0 * By, -vA / B0 * Bz
+    P[9, 0, 0], P[10, 0, 0] = vA * Bz, -vA * By
+    T = periods / vA
+    steps = int(math.ceil(T / (cfl * dx)))
+    return Workload(f"cp_alfven_{n}", nn, 1, (dx, 1.0, 1.0), (x0, 0.0, 0.0), (0, 0, 0), G, RECON["mc2"],
+                    T / steps, steps, P, np.full(shape, float(sigma0)), None,
+                    extra=dict(v_A=vA, period=1.0 / vA, By0=By.copy()))
+
+
+def cylindrical_explosion(n=200, cfl=0.25, sigma0=1e6, t_end=4.0, steps=None, recon="minmod") -> Workload:
+    """The 2D cylindrical explosion of Sec. IV.B: [-6, 6]^2 with n x n cells,
+    Gamma = 4/3, copy boundaries, uniform B^x = 0.05, v = E = 0, sigma0;
+    rho = 0.01, p = 1 inside r = 0.8, rho = p = 0.001 outside r = 1, and in
+    between log-linear in r from the inner to the outer value (the printed
+    interpolation has the two logarithms swapped, which would jump at both
+    radii; the continuous reading is used)."""
+    L = 12.0
+    dx = L / n
+    nn = (n, n, 1)
+    x0 = -6.0 + 0.5 * dx
+    x, y, _ = _coords(nn, 3, (x0, x0, 0.0), (dx, dx, 1.0))
+    r = np.sqrt(x * x + y * y)
+    rin, rout = 0.8, 1.0
+
+    def prof(vin, vout):
+        t = np.clip((r - rin) / (rout - rin), 0.0, 1.0)
+        mid = np.exp((1.0 - t) * math.log(vin) + t * math.log(vout))
+        return np.where(r <= rin, vin, np.where(r >= rout, vout, mid))
+
+    shape = (1, n + 2 * NG, n + 2 * NG)
+    P = np.zeros((14,) + shape)
+    P[0] = np.broadcast_to(prof(0.01, 0.001), shape)
+    P[1] = np.broadcast_to(prof(1.0, 0.001), shape)
+    P[5] = 0.05
+    dt = cfl * dx
+    if steps is None:
+        steps = int(round(t_end / dt))
+        dt = t_end / steps
+    return Workload(f"cylindrical_explosion_{n}^2", nn, 3, (dx, dx, 1.0), (x0, x0, 0.0), (1, 1, 1), 4.0 / 3.0,
+                    RECON[recon], dt, steps, P, np.full(shape, float(sigma0)), None, extra=dict(cfl=cfl))
+
+
+# h(x) = sum_m a_m sin(2 pi n_m . x + c_m) of the tilted slicing (period 1 along each axis)
+SLICING_MODES = [
+    (0.034, (1.0, 0.0, 0.0), 0.3),
+    (0.026, (0.0, 1.0, 0.0), 1.1),
+    (0.022, (0.0, 0.0, 1.0), 2.0),
+    (0.019, (1.0, 1.0, 0.0), 0.7),
+    (0.015, (0.0, 1.0, -1.0), 2.9),
+    (0.015, (1.0, 0.0, 1.0), 4.1),
+]
+
+
+def tilted_slicing_fields(x, y, z, dims=3, q0=0.0, psi0=0.0, phi0=0.0, B0=(0.31, -0.22, 0.17), rho0=1.0,
+                          p0=0.6, xc=(0.07, -0.05, 0.03)):
+    """Flat spacetime in the stationary slicing t = T + h(x) (T, X^i
+    Minkowski; x^i = X^i), with a static Minkowski-frame state: fluid at
+    rest, uniform B0, uniform charge q0 with E = q0 (X - xc)/dims and the
+    pressure p0 + q0^2 |X - xc|^2/(2 dims) that balances q0 E, uniform psi0,
+    phi0.  Returns (metric [16], primitives [14]) at the points, both closed
+    form: gamma_ij = delta_ij - h_i h_j, alpha = (1 - |grad h|^2)^(-1/2),
+    beta^i = alpha^2 h_i, K_ij = alpha h_ij; v^i = alpha h_i,
+    E = alpha (E_flat - h x B0), B = alpha (B0 + h x E_flat), q = alpha q0.
+    Modes with a component along an inactive dimension are dropped."""
+    X = np.broadcast_arrays(x, y, z)
+    shp = X[0].shape
+    kk = 2.0 * math.pi
+    hi = np.zeros((3,) + shp)
+    hij = np.zeros((3, 3) + shp)
+    for a, nv, c in SLICING_MODES:
+        if any(nv[d] != 0.0 for d in range(dims, 3)):
+            continue
+        th = kk * (nv[0] * X[0] + nv[1] * X[1] + nv[2] * X[2]) + c
+        cs, sn = np.cos(th), np.sin(th)
+        for i in range(3):
+            hi[i] += a * kk * nv[i] * cs
+            for j in range(3):
+                hij[i, j] -= a * kk * kk * nv[i] * nv[j] * sn
+    alp = 1.0 / np.sqrt(1.0 - (hi * hi).sum(0))
+    met = np.zeros((16,) + shp)
+    met[0] = alp
+    met[1:4] = alp * alp * hi
+    for s, (i, j) in enumerate([(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]):
+        met[4 + s] = (1.0 if i == j else 0.0) - hi[i] * hi[j]
+        met[10 + s] = alp * hij[i, j]
+    R = np.array([X[d] - xc[d] if d < dims else np.zeros(shp) for d in range(3)])
+    Ef = q0 * R / dims
+    Bf = np.array([np.full(shp, b) for b in B0])
+    P = np.zeros((14,) + shp)
+    P[0] = rho0
+    P[1] = p0 + q0 * q0 * (R * R).sum(0) / (2.0 * dims)
+    P[2:5] = alp * hi
+    P[5:8] = alp * (Bf + np.cross(hi, Ef, axis=0))
+    P[8:11] = alp * (Ef - np.cross(hi, Bf, axis=0))
+    P[11] = phi0
+    P[12] = psi0
+    P[13] = alp * q0
+    return met, P
+
+
+def tilted_slicing(n=16, dims=3, sigma0=100.0, psi0=0.2, phi0=-0.15, recon="weno5", cfl=0.25, steps=2) -> Workload:
+    """A static, uncharged Minkowski state seen from a tilted stationary
+    slicing (see tilted_slicing_fields) on the periodic unit box
+    [-0.5, 0.5)^dims: every shift and extrinsic-curvature term is active and
+    the exact solution is stationary; kappa = 0 keeps the uniform cleaning
+    scalars stationary."""
+    dx = 1.0 / n
+    act = (1 << dims) - 1
+    nn = tuple(n if d < dims else 1 for d in range(3))
+    x0 = tuple(-0.5 + 0.5 * dx if d < dims else 0.0 for d in range(3))
+    x, y, z = _coords(nn, act, x0, (dx,) * 3)
+    met, P = tilted_slicing_fields(x, y, z, dims=dims, psi0=psi0, phi0=phi0)
+    shape = P.shape[1:]
+    return Workload(f"tilted_slicing_{n}_{dims}d", nn, act, (dx,) * 3, x0, (0, 0, 0), 4.0 / 3.0, RECON[recon],
+                    cfl * dx, steps, P, np.full(shape, float(sigma0)), met, kappa=0.0)
+
+
 def by_name(name: str, **kw) -> Workload:
     return {"shocktube": shocktube, "periodic_box": periodic_box, "curved_blob": curved_blob,
-            "sheet_batch": sheet_batch}[name](**kw)
+            "sheet_batch": sheet_batch, "brio_wu": brio_wu, "cp_alfven": cp_alfven,
+            "cylindrical_explosion": cylindrical_explosion, "tilted_slicing": tilted_slicing}[name](**kw)

@@ -129,6 +129,145 @@ def test_curved_256_stage2_sampled(R, orc, recon):
         assert (e <= tol).all(), (key, e)
 
 
+# ------------------------------------------------ whole step at the timed state
+RADIUS = 9          # sub-box half width: a step reaches 6 cells (stage 2 and the final stage, 3 each)
+
+
+def subbox_axis(c, n, bc):
+    """Padded indices (3-cell ghost layout) of one axis of the oracle sub-box
+    around interior cell c, the sub-box's own boundary condition and the
+    sample's index inside it.  Inside the domain the sub-box takes its ghost
+    cells from the GPU state (given); near a copy boundary it is aligned to
+    the boundary and fills its ghosts the same way the domain does; with
+    periodic boundaries it wraps."""
+    m = 2 * RADIUS + 1
+    if bc == 0:                                   # periodic: wrap, ghosts given
+        lo = c - RADIUS
+        return np.array([(lo - 3 + t) % n + 3 for t in range(m + 6)]), 2, RADIUS
+    if c < RADIUS + 3:                            # aligned to the low boundary
+        return np.arange(0, m + 6), 1, c
+    if c > n - 1 - RADIUS - 3:                    # aligned to the high boundary
+        return np.arange(n - m, n + 6), 1, c - (n - m)
+    return np.arange(c - RADIUS, c + RADIUS + 7), 2, RADIUS
+
+
+def take_subbox(t, desc_off, iz, iy, ix):
+    """t[..., iz, iy, ix] of a device tensor in the grid's layout, indices
+    in the 3-cell ghost layout"""
+    oz, oy, ox = desc_off
+    z = torch.as_tensor(iz + oz, device=t.device)
+    y = torch.as_tensor(iy + oy, device=t.device)
+    x = torch.as_tensor(ix + ox, device=t.device)
+    return t[..., z[:, None, None], y[None, :, None], x[None, None, :]].cpu().numpy()
+
+
+def field_scales(R, g, t, interior):
+    """per-field max |t| over interior cells (A25 normalisation; the EM,
+    cleaning and charge fields by at least the largest |E| or |B|)"""
+    I = (slice(None),) + tuple(interior)
+    a = g.from_layout(t)[I].abs().reshape(t.shape[0], -1).amax(1).cpu().numpy()
+    a[5:] = np.maximum(a[5:], a[5:11].max())
+    return a
+
+
+def seam_cells(n, rng, count):
+    """corners, face centres, the centre, cells on both sides of the x
+    sweep's 58-position segment seams and of the 64-cell chunk seams of the
+    stage kernels, then random cells"""
+    cells = set()
+    for i in (0, n - 1):
+        for j in (0, n - 1):
+            for k in (0, n - 1):
+                cells.add((i, j, k))
+    h = n // 2
+    cells.update({(0, h, h), (n - 1, h, h), (h, 0, h), (h, n - 1, h), (h, h, 0), (h, h, n - 1), (h, h, h)})
+    for (j, k) in ((n // 3, n // 5), (n // 2 + 7, n // 4 + 3)):
+        r = k * n + j                                     # row index in the x sweep's row sequence
+        x = (-(r * (n + 6)) - 3) % 58                     # row-sequence position r (n + 6) + x + 3 = 0 mod 58
+        for xx in (x, x + 58):
+            for d in (-1, 0):
+                if 0 <= xx + d < n:
+                    cells.add((xx + d, j, k))
+    for xx in (63, 64, 127, 128):
+        if xx < n:
+            cells.add((xx, n // 2 + 3, n // 3))
+    while len(cells) < count:
+        cells.add(tuple(int(v) for v in rng.integers(0, n, 3)))
+    return sorted(cells)
+
+
+def whole_step_sampled(R, orc, w, pre_steps, cells, tag):
+    """pre_steps IMEX steps of w on the GPU in the benchmark's layout, then
+    one more; the oracle repeats that last step on a sub-box around every
+    sampled cell, from the GPU's state before it, and both U^{n+1} and
+    P^{n+1} at the cell are compared"""
+    n = w.n[0]
+    g = R.grid_for(w, x_align=1)
+    met = None
+    if w.metric is not None:
+        met = g.to_layout(w.metric)
+        g.set_metric(met)
+    sig = g.to_layout(w.sigma)
+    P = g.to_layout(w.P)
+    U = g.prim2con(P)
+    for _ in range(pre_steps):
+        g.step(w.dt, sig, U, P)
+    torch.cuda.synchronize()
+    assert g.failures() == 0
+    off = R.std_offsets(g.desc)
+    boxes = []
+    for (i, j, k) in cells:
+        ax = [subbox_axis(c, n, w.bc[d]) for d, c in enumerate((i, j, k))]
+        ix, iy, iz = ax[0][0], ax[1][0], ax[2][0]
+        boxes.append(dict(U=take_subbox(U, off, iz, iy, ix), P=take_subbox(P, off, iz, iy, ix),
+                          S=take_subbox(sig, off, iz, iy, ix),
+                          M=None if met is None else take_subbox(met, off, iz, iy, ix),
+                          bc=tuple(a[1] for a in ax), at=tuple(a[2] for a in ax)))
+    g.step(w.dt, sig, U, P)
+    torch.cuda.synchronize()
+    assert g.failures() == 0
+    sU = field_scales(R, g, U, w.interior)
+    sP = field_scales(R, g, P, w.interior)
+    eU, eP = np.zeros(14), np.zeros(14)
+    m = 2 * RADIUS + 1
+    for (i, j, k), b in zip(cells, boxes):
+        og = orc.make_grid((m, m, m), 7, w.dx, b["bc"], w.gamma_ad, recon=w.recon, kappa=w.kappa)
+        Uo, Po = np.ascontiguousarray(b["U"]), np.ascontiguousarray(b["P"])
+        M = None if b["M"] is None else np.ascontiguousarray(b["M"])
+        assert orc.step(og, w.dt, np.ascontiguousarray(b["S"]), Uo, Po, M) == 0
+        ai, aj, ak = b["at"]
+        ci = np.array([k + 3, j + 3, i + 3]) + np.array(off)
+        ug = U[:, ci[0], ci[1], ci[2]].cpu().numpy()
+        pg = P[:, ci[0], ci[1], ci[2]].cpu().numpy()
+        eU = np.maximum(eU, np.abs(ug - Uo[:, ak + 3, aj + 3, ai + 3]) / sU)
+        eP = np.maximum(eP, np.abs(pg - Po[:, ak + 3, aj + 3, ai + 3]) / sP)
+    report(f"{tag} U^(n+1) ({len(cells)} cells)", eU, NAMES_U)
+    report(f"{tag} P^(n+1) ({len(cells)} cells)", eP, NAMES_P)
+    tol = tolerances(14, 1e-12, float(w.sigma.max()), w.dt / min(w.dx), 2, t_total=w.dt)
+    assert (eU <= tol).all() and (eP <= tol).all(), (eU, eP, tol)
+
+
+@pytest.mark.parametrize("recon", ["weno5", "mc2"])
+def test_curved_256_whole_step_at_timed_state(R, orc, recon):
+    """The state the benchmark times (256^3 curved blob after 10 IMEX steps,
+    aligned layout): one more full step (stage 1, stage 2, final update and
+    recovery) on the GPU against the oracle's step of each sampled cell's
+    sub-box, taken from the GPU state (eq. IMEX3, Sec. III.B)."""
+    w = W.curved_blob(n=256, recon=recon)
+    cells = seam_cells(256, np.random.default_rng(11), 32)
+    whole_step_sampled(R, orc, w, 10, cells, f"256^3 {recon} step 11")
+
+
+def test_periodic_box_128_whole_step(R, orc):
+    """The 128^3 periodic box: its first IMEX step on the GPU against the
+    oracle's step of wrapped sub-boxes around sampled cells, including the
+    seams of the y/z sweep segments (32 rows at this size)."""
+    w = W.periodic_box(n=128)
+    cells = seam_cells(128, np.random.default_rng(12), 26)
+    cells += [(40, 31, 70), (40, 32, 70), (90, 77, 63), (90, 77, 64)]
+    whole_step_sampled(R, orc, w, 0, sorted(set(cells)), "128^3 periodic step 1")
+
+
 def test_periodic_box_128_conservation(R):
     """The 128^3 periodic box, 10 IMEX steps: the totals of D, S_i, tau,
     B^i and Q (no sources in flat space, flux form) are conserved."""

@@ -21,7 +21,11 @@ def R():
 
 def ogrid(orc, w, **kw):
     return orc.make_grid(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=kw.get("recon", w.recon), x0=w.x0,
-                         kappa=w.kappa)
+                         kappa=w.kappa, speed_mode=w.extra.get("speed_mode", 0))
+
+
+def ggrid(R, w, x_align=0):
+    return R.grid_for(w, x_align=x_align, speed_mode=w.extra.get("speed_mode", 0))
 
 
 def dev(a):
@@ -34,6 +38,8 @@ def host(t):
 
 
 def small_workloads():
+    mode1 = W.curved_blob(n=16, recon="mc2", steps=2, shift=0.05)
+    mode1.extra["speed_mode"] = 1      # alpha sqrt(gamma^dd) -+ beta^d
     return {
         "shocktube_s1e6": W.shocktube(seed=103, sigma0=1e6),
         "shocktube_s1": W.shocktube(seed=101, sigma0=1.0),
@@ -43,6 +49,10 @@ def small_workloads():
         "blob20_minmod": W.curved_blob(n=20, recon="minmod", steps=2),
         "batch4x128": W.sheet_batch(nprob=4, n=128, steps=3),
         "blob16_shift_weno5": W.curved_blob(n=16, recon="weno5", steps=2, shift=0.05),
+        "blob16_shift_mode1": mode1,
+        "slicing16_weno5": W.tilted_slicing(n=16, steps=2),
+        "slicing32_2d_mc2": W.tilted_slicing(n=32, dims=2, recon="mc2", steps=3),
+        "cylexp40_minmod": W.cylindrical_explosion(n=40, steps=3),
     }
 
 
@@ -87,7 +97,7 @@ def test_con2prim_round_trip_parity(R, orc, name):
 
 
 def stage_chain_gpu(R, w, dt, sigma_np, P0, x_align=0):
-    g = R.grid_for(w, x_align=x_align)
+    g = ggrid(R, w, x_align)
     met = None
     if w.metric is not None:
         met = g.to_layout(w.metric)
@@ -140,7 +150,7 @@ def test_one_step_stagewise_parity(R, orc, name, x_align):
 
 
 def run_gpu(R, w, steps, x_align=0):
-    g = R.grid_for(w, x_align=x_align)
+    g = ggrid(R, w, x_align)
     if w.metric is not None:
         met = g.to_layout(w.metric)
         g.set_metric(met)
@@ -167,9 +177,16 @@ def run_oracle(orc, w, steps):
                                                 ("batch4x128", 3, 0), ("shocktube_s1", 20, 0),
                                                 ("shocktube_s1e6", 20, 0), ("blob16_shift_weno5", 3, 0),
                                                 ("box12", 2, 1), ("blob20_weno5", 2, 1), ("batch4x128", 3, 1),
-                                                ("shocktube_s1e6", 20, 1), ("blob16_shift_weno5", 3, 1)])
+                                                ("shocktube_s1e6", 20, 1), ("blob16_shift_weno5", 3, 1),
+                                                ("blob16_shift_mode1", 3, 1), ("slicing16_weno5", 3, 1),
+                                                ("slicing32_2d_mc2", 4, 0), ("cylexp40_minmod", 6, 1),
+                                                ("cylexp40_minmod", 6, 0), ("batch64x2048", 3, 1)])
 def test_multi_step_parity(R, orc, name, steps, x_align):
-    w = small_workloads()[name]
+    """Several whole steps against the oracle.  batch64x2048 is the full
+    64 x 2048 batch: 2048 stage-kernel chunks and 2266 x-sweep segments for
+    1024 persistent waves, so every wave walks two or more work items and
+    its prefetch of the next one is compared too."""
+    w = W.sheet_batch() if name == "batch64x2048" else small_workloads()[name]
     U, P, nf = run_gpu(R, w, steps, x_align)
     Uo, Po, nfo, og = run_oracle(orc, w, steps)
     assert nf == 0 and nfo == 0

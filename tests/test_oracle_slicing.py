@@ -46,78 +46,20 @@ import math
 import numpy as np
 import pytest
 
-# h(x) = sum_m a_m sin(k n_m . x + c_m): smooth, with every first and second
-# derivative (mixed ones included) nonzero somewhere
-_MODES = [
-    (0.034, (1.0, 0.0, 0.0), 0.3),
-    (0.026, (0.0, 1.0, 0.0), 1.1),
-    (0.022, (0.0, 0.0, 1.0), 2.0),
-    (0.019, (1.0, 1.0, 0.0), 0.7),
-    (0.015, (0.0, 1.0, -1.0), 2.9),
-    (0.015, (1.0, 0.0, 1.0), 4.1),
-]
-_K = 2.0 * math.pi
+from paper_2510_18968_amd import workloads as W
 
 
-def slicing_fields(x, y, z, modes=_MODES, dims=3):
-    """grad h and the Hessian of h at the points (x, y, z); modes with a
-    component along an inactive dimension are dropped"""
-    X = (x, y, z)
-    hi = [np.zeros_like(x) for _ in range(3)]
-    hij = [[np.zeros_like(x) for _ in range(3)] for _ in range(3)]
-    for a, n, c in modes:
-        if any(n[d] != 0.0 for d in range(dims, 3)):
-            continue
-        th = _K * (n[0] * X[0] + n[1] * X[1] + n[2] * X[2]) + c
-        cs, sn = np.cos(th), np.sin(th)
-        for i in range(3):
-            hi[i] = hi[i] + a * _K * n[i] * cs
-            for j in range(3):
-                hij[i][j] = hij[i][j] - a * _K * _K * n[i] * n[j] * sn
-    return np.array(hi), np.array(hij)
-
-
-def slicing_state(n, dims, q0, sig, psi0, phi0, B0=(0.31, -0.22, 0.17), rho0=1.0, p0=0.6):
-    """metric (16 fields) and primitives (14 fields) on the padded grid"""
+def slicing_state(n, dims, q0, sig, psi0, phi0):
+    """metric (16 fields), primitives (14 fields) and sigma on the padded grid
+    of the unit box [-0.5, 0.5]^dims (closed forms in
+    workloads.tilted_slicing_fields)"""
     dx = 1.0 / n
     c = -0.5 + dx * (np.arange(-3, n + 3) + 0.5)
-    shape = [n + 6 if d < dims else 1 for d in range(3)]
     ax = [c if d < dims else np.zeros(1) for d in range(3)]
     Z, Y, Xg = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
-    hi, hij = slicing_fields(Xg, Y, Z, dims=dims)
-    h2 = (hi * hi).sum(0)
-    assert h2.max() < 0.4
-    alp = 1.0 / np.sqrt(1.0 - h2)
-    met = np.zeros((16,) + Xg.shape)
-    met[0] = alp
-    for i in range(3):
-        met[1 + i] = alp * alp * hi[i]
-    sym = [(0, 0), (0, 1), (0, 2), (1, 1), (1, 2), (2, 2)]
-    for s, (i, j) in enumerate(sym):
-        met[4 + s] = (1.0 if i == j else 0.0) - hi[i] * hi[j]
-        met[10 + s] = alp * hij[i][j]
-    # Minkowski-frame fields: E_flat = q0 (X - Xc)/3 solves div E = q0
-    Xc = (0.07, -0.05, 0.03)
-    R = np.array([Xg - Xc[0], Y - Xc[1], Z - Xc[2]])
-    if dims < 3:
-        # fewer dimensions: the field of a uniform slab charge along the active ones
-        for d in range(dims, 3):
-            R[d] = 0.0
-    Ef = q0 * R / dims
-    Bf = np.array([np.full(Xg.shape, b) for b in B0])
-    Ecal = Ef - np.cross(hi, Bf, axis=0)
-    Bcal = Bf + np.cross(hi, Ef, axis=0)
-    P = np.zeros((14,) + Xg.shape)
-    P[0] = rho0
-    P[1] = p0 + q0 * q0 * (R * R).sum(0) / (2.0 * dims)
-    P[2:5] = alp * hi
-    P[5:8] = alp * Bcal
-    P[8:11] = alp * Ecal
-    P[11] = phi0
-    P[12] = psi0
-    P[13] = alp * q0
-    sigma = np.full(Xg.shape, sig)
-    return met, P, sigma, dx, shape
+    met, P = W.tilted_slicing_fields(Xg, Y, Z, dims=dims, q0=q0, psi0=psi0, phi0=phi0)
+    assert met[0].max() < 1.3     # |grad h|^2 < 0.41
+    return met, P, np.full(Xg.shape, sig), dx, Xg.shape
 
 
 def rhs_residual(orc, n, dims, recon, **kw):
