@@ -3,7 +3,11 @@
 Normalisation: each field's max |gpu - oracle| over interior cells is divided
 by the field's max |oracle|; the electromagnetic, cleaning and charge fields
 (indices 5..13 of both P and U) are divided by at least the largest E or B
-magnitude, since phi, psi and q start at zero and E can vanish.
+magnitude, since phi, psi and q start at zero and E can vanish.  The
+components of the velocity (P indices 2..4) or of the momentum (U indices
+1..3) are divided by at least the largest component of the same vector: a
+component that vanishes in exact arithmetic (v^z of a flow in the x-y plane)
+holds only rounding on both sides.
 """
 import numpy as np
 
@@ -15,21 +19,29 @@ NAMES_U = ["D", "Sx", "Sy", "Sz", "tau", "Bx", "By", "Bz", "Ex", "Ey", "Ez", "Ph
 EPS = 2.0 ** -53
 
 
-def rel_errors(gpu, ref, interior, em=True, floor=0.0):
+VEC = {"P": (2, 5), "U": (1, 4)}
+
+
+def rel_errors(gpu, ref, interior, em=True, floor=0.0, kind=None):
     """per-field max |gpu - ref| / scale; floor: lower bound of every scale
-    (R arrays use |E|/(gamma dt), the size of the E change they encode)"""
+    (R arrays use |E|/(gamma dt), the size of the E change they encode);
+    kind "P" or "U" names the array, for the vector normalisation"""
     gpu = np.asarray(gpu)
     ref = np.asarray(ref)
     nf = ref.shape[0]
     sl = (slice(None),) + tuple(interior)
     g, r = gpu[sl], ref[sl]
     em_scale = float(np.abs(r[5:11]).max()) if (em and nf == 14) else 0.0
+    lo, hi = VEC[kind] if (kind and nf == 14) else (0, 0)
+    vec_scale = float(np.abs(r[lo:hi]).max()) if hi > lo else 0.0
     out = []
     for f in range(nf):
         d = float(np.abs(g[f] - r[f]).max())
         s = max(float(np.abs(r[f]).max()), floor)
         if em and nf == 14 and f in EM:
             s = max(s, em_scale)
+        if lo <= f < hi:
+            s = max(s, vec_scale)
         out.append(d / s if s > 0 else d)
     return np.array(out)
 

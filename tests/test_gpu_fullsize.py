@@ -123,7 +123,8 @@ def test_curved_256_stage2_sampled(R, orc, recon):
         got = np.array([a for a, b in errs[key]]).T.reshape(-1, 1, 1, len(cells))
         ref = np.array([b for a, b in errs[key]]).T.reshape(-1, 1, 1, len(cells))
         isR = key == "R2"
-        e = rel_errors(got, ref, (slice(None),) * 3, em=not isR, floor=escale if isR else 0.0)
+        e = rel_errors(got, ref, (slice(None),) * 3, em=not isR, floor=escale if isR else 0.0,
+                       kind=None if isR else key[0])
         report(f"256^3 {recon} stage 2 sampled {key} ({len(cells)} cells)", e, names)
         tol = tolerances(len(e), 1e-12, float(w.sigma.max()), w.dt / w.dx[0], 1, t_total=w.dt)
         assert (e <= tol).all(), (key, e)
@@ -312,7 +313,7 @@ def test_curved_256_round_trip_after_evolution(R):
     assert g.failures() == 0
     I = tuple(w.interior)
     assert int((g.from_layout(st)[I] != 0).sum()) == 0
-    e = rel_errors(g.from_layout(guess).cpu().numpy(), g.from_layout(P).cpu().numpy(), I)
+    e = rel_errors(g.from_layout(guess).cpu().numpy(), g.from_layout(P).cpu().numpy(), I, kind="P")
     report("256^3 round trip after 5 steps", e, NAMES_P)
     assert e.max() <= 1e-12
 

@@ -66,7 +66,7 @@ def test_prim2con_parity(R, orc, name):
         g.set_metric(met)
     U = host(g.prim2con(dev(w.P)))
     Uo = orc.prim2con(og, w.P, w.metric)
-    e = rel_errors(U, Uo, orc.interior(og))
+    e = rel_errors(U, Uo, orc.interior(og), kind="U")
     report(f"prim2con {name}", e, NAMES_U)
     assert e.max() <= 1e-14
 
@@ -90,10 +90,10 @@ def test_con2prim_round_trip_parity(R, orc, name):
     Po, sto, _, nf = orc.con2prim(og, Uo, guess, w.metric)
     I = orc.interior(og)
     assert nf == 0 and (host(st)[I] == 0).all()
-    e = rel_errors(P, Po, I)
+    e = rel_errors(P, Po, I, kind="P")
     report(f"con2prim {name}", e, NAMES_P)
     assert e.max() <= TOL
-    assert rel_errors(P, w.P, I).max() <= TOL
+    assert rel_errors(P, w.P, I, kind="P").max() <= TOL
 
 
 def stage_chain_gpu(R, w, dt, sigma_np, P0, x_align=0):
@@ -142,7 +142,7 @@ def test_one_step_stagewise_parity(R, orc, name, x_align):
     for key in ("U0", "P1", "R1", "U2", "P2", "R2", "U3", "P3"):
         names = NAMES_P if key.startswith("P") else (NAMES_U if key.startswith("U") else ["x", "y", "z"])
         isR = key.startswith("R")
-        e = rel_errors(gpu[key], ref[key], I, em=not isR, floor=escale if isR else 0.0)
+        e = rel_errors(gpu[key], ref[key], I, em=not isR, floor=escale if isR else 0.0, kind=None if isR else key[0])
         report(f"{name} {key}", e, names)
         nflux = {"U2": 1, "P2": 1, "R2": 1, "U3": 2, "P3": 2}.get(key, 1)
         tol = tolerances(len(e), TOL, float(w.sigma.max()), w.dt / min(w.dx), nflux, t_total=w.dt)
@@ -191,7 +191,7 @@ def test_multi_step_parity(R, orc, name, steps, x_align):
     Uo, Po, nfo, og = run_oracle(orc, w, steps)
     assert nf == 0 and nfo == 0
     I = orc.interior(og)
-    eU, eP = rel_errors(U, Uo, I), rel_errors(P, Po, I)
+    eU, eP = rel_errors(U, Uo, I, kind="U"), rel_errors(P, Po, I, kind="P")
     report(f"{name} {steps} steps U", eU, NAMES_U)
     report(f"{name} {steps} steps P", eP, NAMES_P)
     tol = tolerances(14, TOL, float(w.sigma.max()), w.dt / min(w.dx), 2 * steps, t_total=steps * w.dt)
@@ -208,7 +208,7 @@ def test_shocktube_full_run_parity(R, orc, seed, sigma0):
     Uo, Po, nfo, og = run_oracle(orc, w, w.steps)
     assert nf == 0 and nfo == 0
     I = orc.interior(og)
-    eU, eP = rel_errors(U, Uo, I), rel_errors(P, Po, I)
+    eU, eP = rel_errors(U, Uo, I, kind="U"), rel_errors(P, Po, I, kind="P")
     report(f"shocktube seed={seed} sigma={sigma0:g} U", eU, NAMES_U)
     report(f"shocktube seed={seed} sigma={sigma0:g} P", eP, NAMES_P)
     tol = tolerances(14, TOL, sigma0, w.dt / w.dx[0], 2 * w.steps, t_total=w.steps * w.dt)

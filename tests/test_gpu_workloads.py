@@ -49,7 +49,7 @@ def compare(tag, w, steps, gpu, ref, og):
     Uo, Po, nfo, _ = ref
     assert nf == 0 and nfo == 0, (nf, nfo)
     I = og if isinstance(og, tuple) else None
-    eU, eP = rel_errors(U, Uo, I), rel_errors(P, Po, I)
+    eU, eP = rel_errors(U, Uo, I, kind="U"), rel_errors(P, Po, I, kind="P")
     report(f"{tag} U", eU, NAMES_U)
     report(f"{tag} P", eP, NAMES_P)
     tol = tolerances(14, TOL, float(w.sigma.max()), w.dt / min(w.dx), 2 * steps, t_total=steps * w.dt)
