@@ -39,9 +39,12 @@ def build(force: bool = True) -> str:
 
 class Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("active", C.c_int32), ("ng", C.c_int32), ("bc", C.c_int32 * 3),
-                ("recon", C.c_int32), ("c2p_maxit", C.c_int32), ("speed_mode", C.c_int32), ("pad_", C.c_int32),
+                ("recon", C.c_int32), ("c2p_maxit", C.c_int32), ("speed_mode", C.c_int32),
+                ("sigma_model", C.c_int32),
                 ("x0", C.c_double * 3), ("dx", C.c_double * 3),
-                ("gamma_ad", C.c_double), ("kappa", C.c_double), ("c2p_tol", C.c_double)]
+                ("gamma_ad", C.c_double), ("kappa", C.c_double), ("c2p_tol", C.c_double),
+                ("sigma0", C.c_double), ("sigma_exp", C.c_double), ("sigma_Datmo", C.c_double),
+                ("rho_atmo", C.c_double), ("K_atmo", C.c_double)]
 
 
 _lib = None
@@ -76,10 +79,11 @@ def lib():
             "orc_stage1": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp, ip, ip]),
             "orc_stage2": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]),
             "orc_final": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp, dp, dp, ip, ip]),
-            "orc_step": (C.c_long, [gp, dp, C.c_double, dp, dp, dp]),
+            "orc_step": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, ip]),
             "orc_step_tangent": (C.c_long, [gp, dp, C.c_double, dp, dp, dp, dp, dp, dp]),
             "orc_max_signal_speed": (C.c_double, [gp, dp]),
             "orc_num_threads": (C.c_int, []),
+            "orc_set_num_threads": (None, [C.c_int]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -103,8 +107,17 @@ def _ip(a):
     return a.ctypes.data_as(C.POINTER(C.c_int32))
 
 
+SIGMA_FIELD, SIGMA_POWER, SIGMA_DYNAMO = 0, 1, 2
+ATMO_FACTOR = 1.01
+
+
 def make_grid(n, active, dx, bc, gamma_ad, recon=REC_WENO5, kappa=1.0, x0=(0.0, 0.0, 0.0), ng=3,
-              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0) -> Grid:
+              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0, sigma_model=0, sigma0=0.0, sigma_exp=0.0,
+              sigma_Datmo=0.0, rho_atmo=0.0, K_atmo=0.0) -> Grid:
+    """sigma_model 0: the given per-cell sigma field; 1: sigma0 D^sigma_exp
+    (eq. sigma_evol); 2: sigma0 max(1 - sigma_Datmo/D, 0)^2 (eq.
+    dynamo_sigma).  rho_atmo > 0: the step-end atmosphere (rho_atmo, p =
+    K_atmo rho_atmo^Gamma, v = 0) below D = ATMO_FACTOR sqrt(gamma) rho_atmo."""
     g = Grid()
     for d in range(3):
         g.n[d] = int(n[d])
@@ -114,6 +127,9 @@ def make_grid(n, active, dx, bc, gamma_ad, recon=REC_WENO5, kappa=1.0, x0=(0.0, 
     g.active, g.ng, g.recon = int(active), int(ng), int(recon)
     g.c2p_maxit, g.speed_mode = int(c2p_maxit), int(speed_mode)
     g.gamma_ad, g.kappa, g.c2p_tol = float(gamma_ad), float(kappa), float(c2p_tol)
+    g.sigma_model, g.sigma0, g.sigma_exp, g.sigma_Datmo = int(sigma_model), float(sigma0), float(sigma_exp), \
+        float(sigma_Datmo)
+    g.rho_atmo, g.K_atmo = float(rho_atmo), float(K_atmo)
     return g
 
 
@@ -280,9 +296,11 @@ def final(g, dt, sigma, Un, F1, P2, R1, R2, metric=None):
     return dict(U=U3, P=P3, status=st, iters=it, nfail=nf)
 
 
-def step(g, dt, sigma, U, P, metric=None):
-    """One IMEX-SSP2(2,2,2) step in place; returns the number of failed cells."""
-    return lib().orc_step(C.byref(g), _p(metric), dt, _p(sigma), _p(U), _p(P))
+def step(g, dt, sigma, U, P, metric=None, status=None):
+    """One IMEX-SSP2(2,2,2) step in place; returns the number of failed cells.
+    status ([Np] int32, optional): the final recovery's per-cell status
+    (2: atmosphere)."""
+    return lib().orc_step(C.byref(g), _p(metric), dt, _p(sigma), _p(U), _p(P), _ip(status))
 
 
 def step_tangent(g, dt, sigma, U, dU, P, dsigma=None, metric=None):
@@ -300,3 +318,8 @@ def max_signal_speed(g, metric=None):
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel loops."""
+    lib().orc_set_num_threads(int(n))

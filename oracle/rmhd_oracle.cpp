@@ -24,6 +24,8 @@
  *   stiff split ........... Sec. III.A (F_E / R_E split)
  *   implicit E solve ...... eq. 3D_NR (3D Newton-Raphson)
  *   coupled recovery ...... Sec. III.B steps (i)-(v)
+ *   conductivity models ... eq. sigma_evol (Sec. IV.A), eq. dynamo_sigma and
+ *                           the artificial atmosphere (Sec. IV.E)
  *
  * Where the paper is silent or garbled the readings below are used (each is
  * listed with its reason in the design notes of the repository):
@@ -41,7 +43,17 @@
  *   - recovery stops when |dp| <= tol p and max|dv^i| <= tol;
  *   - a face state with rho<=0, p<=0 or v^2>=1 falls back to first order;
  *   - derivatives through a limiter or a fallback are those of the branch
- *     taken (at a tie or a zero slope the returned branch, not an average).
+ *     taken (at a tie or a zero slope the returned branch, not an average);
+ *   - a conductivity model sigma(D) takes the conserved D of the state it
+ *     acts on: in an implicit solve the D of the stage's explicit state (the
+ *     solve does not change D); in the charge flux of F(U(s)) the D of the
+ *     stage primitives at each cell centre (sqrt(gamma) rho W, ghost cells
+ *     included);
+ *   - the artificial atmosphere acts at the end of each step: a cell whose
+ *     assembled D is below 1.01 sqrt(gamma) rho_atmo gets the hydro part
+ *     (D, S_i, tau) of the atmosphere state (rho_atmo, p = K_atmo
+ *     rho_atmo^Gamma, v = 0) with its own E and B, is recovered from it and
+ *     flagged with status 2 (never silently).
  *
  * Parity status: every function here is pinned by tests in tests/ against
  * closed forms, library routines, invariants or brute force, except the
@@ -97,6 +109,11 @@ inline Dual sqrt(Dual a) {
     return Dual(s, a.d / (2.0 * s));
 }
 inline Dual fabs(Dual a) { return a.v < 0 ? -a : a; }
+/* x^e for a constant exponent e: d(x^e) = e x^(e-1) dx */
+inline double pw(double x, double e) { return std::pow(x, e); }
+inline Dual pw(Dual x, double e) {
+    return Dual(std::pow(x.v, e), e == 0.0 ? 0.0 : e * std::pow(x.v, e - 1.0) * x.d);
+}
 
 using std::sqrt;
 using std::fabs;
@@ -849,10 +866,28 @@ struct Grid {                 /* mirrors oracle.py's ctypes structure */
     int32_t recon;
     int32_t c2p_maxit;
     int32_t speed_mode;
-    int32_t pad_;
+    int32_t sigma_model;      /* 0: the given sigma field; 1: eq. sigma_evol; 2: eq. dynamo_sigma */
     double x0[3], dx[3];
     double gamma_ad, kappa, c2p_tol;
+    double sigma0, sigma_exp, sigma_Datmo;   /* parameters of the conductivity models */
+    double rho_atmo, K_atmo;                 /* artificial atmosphere (rho_atmo = 0: none) */
 };
+
+/* Conductivity of a cell from the conserved rest-mass density D of its state:
+ * model 1 is eq. sigma_evol, sigma = sigma0 D^gamma (Sec. IV.A), model 2 is
+ * eq. dynamo_sigma, sigma = sigma0 max(1 - D_atmo/D, 0)^2 (Sec. IV.E); model
+ * 0 returns the given per-cell field. */
+template <class T> T conductivity(const Grid& gr, T sig_field, T D) {
+    if (gr.sigma_model == 1) return gr.sigma0 * pw(D, gr.sigma_exp);
+    if (gr.sigma_model == 2) {
+        T t = tmax(1.0 - gr.sigma_Datmo / D, T(0.0));
+        return gr.sigma0 * t * t;
+    }
+    return sig_field;
+}
+
+/* cells whose D lies below ATMO_FACTOR sqrt(gamma) rho_atmo are atmosphere */
+constexpr double ATMO_FACTOR = 1.01;
 
 struct Geo {
     int g[3], np[3];
@@ -1006,7 +1041,13 @@ void explicit_rhs(const Grid& gr, const Geo& ge, const T* metric, const T* Pst, 
                             load_metric(metric, Np, oc, mc);
                             Metric<T> mm;
                             metric_point(mc, mm);
-                            cell_current(mm, G, Pc, sig[oc], Jc[side]);
+                            T sc = sig[oc];
+                            if (gr.sigma_model != 0) {
+                                T Uc[NF];
+                                prim2con(mm, G, Pc, Uc);
+                                sc = conductivity(gr, sc, Uc[U_D]);
+                            }
+                            cell_current(mm, G, Pc, sc, Jc[side]);
                         }
                         Jf = 0.5 * (Jc[0][d] + Jc[1][d]);
                     }
@@ -1038,6 +1079,7 @@ inline double gam_imex() { return 1.0 - 1.0 / std::sqrt(2.0); }
 
 /* copy of the primitives with ghosts filled, and a ghost-filled copy of sigma */
 template <class T> std::vector<T> filled_copy(const Grid& gr, const Geo& ge, const T* a, int nf) {
+    if (!a) return std::vector<T>((size_t)nf * ge.Np, T(0.0));   /* no sigma field: the models set it */
     std::vector<T> c(a, a + (size_t)nf * ge.Np);
     ghost_fill(gr, ge, c.data(), nf);
     return c;
@@ -1065,7 +1107,8 @@ long solve_all(const Grid& gr, const Geo& ge, const T* metric, const T* Uin, con
                 }
                 for (int c = 0; c < 3; ++c) Es[c] = Estar[(long)c * Np + o];
                 int it = 0;
-                int st = coupled_solve(m, gr.gamma_ad, U, Es, T(adt), sig[o], Pgs, gr.c2p_tol, gr.c2p_maxit, P, E,
+                const T sc = adt == 0.0 ? T(0.0) : conductivity(gr, sig ? sig[o] : T(0.0), U[U_D]);
+                int st = coupled_solve(m, gr.gamma_ad, U, Es, T(adt), sc, Pgs, gr.c2p_tol, gr.c2p_maxit, P, E,
                                        &it);
                 for (int a = 0; a < NF; ++a) Pout[(long)a * Np + o] = P[a];
                 for (int c = 0; c < 3; ++c) Eout[(long)c * Np + o] = E[c];
@@ -1153,8 +1196,39 @@ long final_update(const Grid& gr, const T* metric, double dt, const T* sig, cons
             Unp1[(long)(U_E + c) * Np + o] =
                 Unp1[(long)(U_E + c) * Np + o] + 0.5 * dt * (R1[(long)c * Np + o] + R2[(long)c * Np + o]);
     });
+    /* artificial atmosphere (Sec. IV.E): the hydro part of a cell whose D is
+     * below ATMO_FACTOR sqrt(gamma) rho_atmo becomes that of the atmosphere
+     * state (rho_atmo, p = K_atmo rho_atmo^Gamma, v = 0) with the cell's own
+     * E, B and cleaning fields; the recovery below then returns that state */
+    std::vector<char> atmo;
+    if (gr.rho_atmo > 0.0) {
+        atmo.assign((size_t)Np, 0);
+        for_interior(gr, ge, [&](long o) {
+            T mf[NM];
+            load_metric(metric, Np, o, mf);
+            Metric<T> m;
+            metric_point(mf, m);
+            if (!(val(Unp1[(long)U_D * Np + o]) < ATMO_FACTOR * val(m.sqrtg) * gr.rho_atmo)) return;
+            atmo[(size_t)o] = 1;
+            T Pa[NF], Ua[NF];
+            Pa[P_RHO] = T(gr.rho_atmo);
+            Pa[P_PRS] = T(gr.K_atmo * std::pow(gr.rho_atmo, gr.gamma_ad));
+            for (int i = 0; i < 3; ++i) Pa[P_V + i] = T(0.0);
+            for (int a = P_B; a < NF; ++a) Pa[a] = Unp1[(long)a * Np + o] / m.sqrtg;
+            prim2con(m, gr.gamma_ad, Pa, Ua);
+            for (int a = U_D; a <= U_TAU; ++a) Unp1[(long)a * Np + o] = Ua[a];
+        });
+    }
     std::vector<T> Ef((size_t)3 * Np, T(0.0));
-    return solve_all(gr, ge, metric, Unp1, Unp1 + (long)U_E * Np, 0.0, sig, P2, Pnp1, Ef.data(), status, iters);
+    std::vector<int32_t> st((size_t)Np, 0);
+    long nf = solve_all(gr, ge, metric, Unp1, Unp1 + (long)U_E * Np, 0.0, sig, P2, Pnp1, Ef.data(), st.data(), iters);
+    if (!atmo.empty())
+        for_interior(gr, ge, [&](long o) {
+            if (atmo[(size_t)o] && st[(size_t)o] >= 0) st[(size_t)o] = 2;
+        });
+    if (status)
+        for_interior(gr, ge, [&](long o) { status[o] = st[(size_t)o]; });
+    return nf;
 }
 
 }  // namespace orc
@@ -1298,8 +1372,10 @@ long orc_final(const Grid* gr, const double* metric, double dt, const double* si
     return final_update(*gr, metric, dt, sig, Un, F1, P2, R1, R2, Unp1, Pnp1, status, iters);
 }
 
-/* one full step in place on (U, P); returns the number of failed cells */
-long orc_step(const Grid* gr, const double* metric, double dt, const double* sig, double* U, double* P) {
+/* one full step in place on (U, P); returns the number of failed cells;
+ * status (optional, [Np]): the final recovery's status (2: atmosphere) */
+long orc_step(const Grid* gr, const double* metric, double dt, const double* sig, double* U, double* P,
+              int32_t* status) {
     Geo ge(*gr);
     size_t n = (size_t)NF * ge.Np;
     std::vector<double> P1(P, P + n), U1(U, U + n), R1((size_t)3 * ge.Np, 0.0), U2(U, U + n), P2(P, P + n),
@@ -1310,7 +1386,7 @@ long orc_step(const Grid* gr, const double* metric, double dt, const double* sig
                  (int32_t*)nullptr, (int32_t*)nullptr);
     std::vector<double> Un(U, U + n);
     nf += final_update(*gr, metric, dt, sig, Un.data(), F1.data(), P2.data(), R1.data(), R2.data(), U, P,
-                       (int32_t*)nullptr, (int32_t*)nullptr);
+                       status, (int32_t*)nullptr);
     return nf;
 }
 
@@ -1376,6 +1452,15 @@ int orc_num_threads(void) {
     return omp_get_max_threads();
 #else
     return 1;
+#endif
+}
+
+// thread count of the later parallel loops (timing of the CPU baseline)
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
 #endif
 }
 
