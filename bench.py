@@ -1,14 +1,22 @@
 #!/usr/bin/env python3
 """Benchmark of the resistive GRMHD IMEX-SSP2(2,2,2) stage on one MI355X.
 
-Metric: zone-updates/s per IMEX stage (interior cells x stage-2 applications
+Metric: zone-updates/s per IMEX stage (interior cells per stage-2 application
 per second) on the 256^3 static curved background with a magnetised blob,
 FP64, WENO5 + HLLE, after 10 steps of evolution (so that the stiff recovery
 does real work).  One timed "step" is one application of IMEX stage 2: ghost
 fill, reconstruction, HLLE fluxes, flux divergence + sources + RK combination
 and the coupled implicit-E / primitive recovery, i.e. every row of the hot
-path.  A full IMEX step (two such flux stages plus the pointwise stage 1) is
-timed as well and reported beside it.
+path.  Each application is bracketed by HIP events on the library's stream
+with the library's own launch timers off; `value` is the interior cell count
+over the median application time.  Per-kernel times come from a separate
+pass with the launch timers on.
+
+Beside the headline it reports the full IMEX step, MC2, the mixed form (with
+its per-field error after 50 steps), the forward + adjoint rollout of the
+64 x 2048 batch, GPU and oracle timings of the 400-cell shocktubes, the 128^3
+periodic box and the 64 x 2048 batch, and the oracle (the plain FP64 CPU
+implementation of the same method) timed on the GPU's timed state.
 
 Prints one JSON line.  Usage: python bench.py [--steps K] [--warmup W]
 """
@@ -16,8 +24,8 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
+import statistics
 import sys
 import time
 
@@ -32,16 +40,26 @@ METRIC = "zone-updates/s per IMEX stage, FP64 vs mixed at 256^3; fwd+adjoint s/s
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_VECTOR_TFLOPS = 78.6
 
+# Algorithmic HBM bytes of one IMEX stage per interior zone, curved metric:
+# every stage input and output word moved once (reads U^n 14, E(1) 3, the
+# hydro primitives 5, R1 3, sigma 1, metric 10; writes U(2) 14, the hydro
+# primitives 5, R2 3: 58 words).
+STAGE_FLOOR_BYTES = 464
+
 # Per interior cell and launch of each kernel class on the 256^3 curved WENO5
 # workload (zero shift and extrinsic curvature, so the metric read is alpha and
 # gamma_ij, 7 words):
-#  * algorithmic HBM bytes: each word the kernel must read or write, once;
-#  * FP64 flops: executed, from the SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64
-#    counters (FMA = 2 flops, 64 lanes per wave instruction);
-#  * measured HBM traffic: FETCH_SIZE + WRITE_SIZE of the same launch, scaled by
-#    what the counters read for a streaming kernel of known size.
-# The flops and traffic figures belong to the kernels as profiled (the file
-# names under profiles/ say which); they are re-measured when a kernel changes.
+#  * BYTES_PER_CELL: each word the kernel as designed reads or writes, once
+#    (this includes the 14-field flux-divergence accumulator between the
+#    launches, which the stage floor above does not);
+#  * FLOPS_PER_CELL: executed FP64 flops, from the
+#    SQ_INSTS_VALU_{ADD,MUL,FMA,TRANS}_F64 counters (FMA = 2 flops, 64 lanes
+#    per wave instruction);
+#  * TRAFFIC_BYTES_PER_CELL: FETCH_SIZE + WRITE_SIZE of the same launch,
+#    scaled by what the counters read for a streaming kernel of known size.
+# The flops and traffic figures belong to the kernels as profiled
+# (profiles/counters_curved256_weno5.md); they are re-measured when a kernel
+# changes.
 BYTES_PER_CELL = {
     # P 14 + sigma 1 + metric 7 read, rhs 14 written
     "flux_x": 8 * (14 + 1 + 7 + 14),
@@ -68,16 +86,20 @@ def parse():
     ap.add_argument("--n", type=int, default=256, help="cells per dimension (default: the 256^3 workload)")
     ap.add_argument("--recon", default="weno5", choices=["weno5", "mc2", "minmod"])
     ap.add_argument("--evolve", type=int, default=10, help="IMEX steps before timing")
-    ap.add_argument("--full-steps", type=int, default=3, help="timed full IMEX steps (reported beside)")
+    ap.add_argument("--full-steps", type=int, default=5, help="timed full IMEX steps (reported beside)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", default="128,128,96", help="oracle sub-box (nx,ny,nz) for cpu_baseline")
     ap.add_argument("--cpu-reps", type=int, default=12, help="timed oracle stage-2 applications for cpu_baseline")
+    ap.add_argument("--cpu-single", default="48,48,32", help="oracle sub-box of the single-thread figure")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also launch a plain device copy of known size (for HBM counter calibration)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision (FP32 stencil) form")
     ap.add_argument("--mixed-steps", type=int, default=50, help="steps of the FP64-vs-mixed accuracy run")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward + adjoint rollout timing")
     ap.add_argument("--no-other-recon", action="store_true", help="skip timing the other reconstruction (MC2/WENO5)")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the shocktube / periodic box / batch timings (GPU and oracle)")
+    ap.add_argument("--no-breakdown", action="store_true", help="skip the per-kernel timing pass")
     ap.add_argument("--adjoint-steps", type=int, default=200, help="steps of the differentiated rollout")
     return ap.parse_args()
 
@@ -86,62 +108,118 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(w, dt, sample, reps):
-    """The oracle, as it stands, on a sub-box of the same workload: the
-    central nx x ny x nz cells of the seeded initial data with their real
-    neighbours as ghost cells (held fixed), advanced two oracle steps, then
-    `reps` timed oracle stage-2 applications at that state."""
-    import oracle
-
-    oracle.build(force=False)
-    nx, ny, nz = sample
-    N = w.n[0]
-    c = N // 2
-    lo = [c - nx // 2, c - ny // 2, c - nz // 2]
-    sl = (slice(lo[2], lo[2] + nz + 6), slice(lo[1], lo[1] + ny + 6), slice(lo[0], lo[0] + nx + 6))
-    P = np.ascontiguousarray(w.P[(slice(None),) + sl])
-    met = np.ascontiguousarray(w.metric[(slice(None),) + sl])
-    sig = np.ascontiguousarray(w.sigma[sl])
-    x0 = tuple(w.x0[d] + lo[d] * w.dx[d] for d in range(3))
-    og = oracle.make_grid((nx, ny, nz), 7, w.dx, (oracle.BC_GIVEN,) * 3, w.gamma_ad, recon=w.recon, x0=x0)
-    U = oracle.prim2con(og, P, met)
-    for _ in range(2):
-        oracle.step(og, dt, sig, U, P, met)
-    s1 = oracle.stage1(og, dt, sig, U, P, met)
-    t0 = time.perf_counter()
-    for _ in range(reps):
-        s2 = oracle.stage2(og, dt, sig, U, s1["P1"], s1["R1"], met)
-    t = time.perf_counter() - t0
-    cells = nx * ny * nz * reps
-    return {"value": cells / t, "unit": "zone-updates/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{reps} applications of IMEX stage 2 on the central {nx}x{ny}x{nz} cells of the 256^3 "
-                      f"curved-blob workload (real neighbour ghosts, held fixed), after two oracle steps; "
-                      f"{t:.2f} s timed, {int(s2['nfail'])} failed cells"}
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-def roofline(per_launch, kern, ncell):
-    """Roofline of the kernel class with the largest total time: its binding
-    ceiling is the larger of the HBM time of its algorithmic bytes and the FP64
-    time of its flops; both fractions are reported."""
-    dominant = max(per_launch, key=lambda k: kern[k][0])
-    t = per_launch[dominant] * 1e-3
-    nbytes = BYTES_PER_CELL.get(dominant, 0) * ncell
-    flops = FLOPS_PER_CELL.get(dominant, 0.0) * ncell
+def timed_calls(torch, fn, steps, warmup):
+    """Per-call times (ms) of `steps` calls of fn, each bracketed by HIP
+    events on the current stream (the stream the library launches on)."""
+    for _ in range(warmup):
+        fn()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for i in range(steps):
+        fn()
+        ev[i + 1].record()
+    torch.cuda.synchronize()
+    return [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)], ev[0].elapsed_time(ev[-1])
+
+
+def stage_roofline(ms, ncell, kernels_ms):
+    """Stage-level roofline: the stage floor bytes and the counted FP64 flops
+    of the four launches over the median stage time, with the per-kernel
+    figures as a breakdown."""
+    t = ms * 1e-3
+    nbytes = STAGE_FLOOR_BYTES * ncell
+    flops = sum(FLOPS_PER_CELL.values()) * ncell
+    traffic = sum(TRAFFIC_BYTES_PER_CELL.values()) * ncell
     t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
     t_alu = flops / (PEAK_FP64_VECTOR_TFLOPS * 1e12)
     gbs = nbytes / t / 1e9
-    tfs = flops / t / 1e12
-    traffic = TRAFFIC_BYTES_PER_CELL.get(dominant)
-    if t_alu > t_hbm:
-        roof = {"bound": "alu", "achieved": tfs, "peak": PEAK_FP64_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                "frac": tfs / PEAK_FP64_VECTOR_TFLOPS}
-    else:
-        roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS}
-    roof["traffic"] = None if traffic is None else traffic * ncell / 1e9
-    roof.update({"traffic_unit": "GB per launch (FETCH_SIZE + WRITE_SIZE, calibrated)", "kernel": dominant,
-                 "kernel_ms": t * 1e3, "algorithmic_GB": nbytes / 1e9, "hbm_frac": gbs / PEAK_HBM_GBS,
-                 "fp64_TFLOP": flops / 1e12, "fp64_frac": tfs / PEAK_FP64_VECTOR_TFLOPS})
+    roof = {"bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+            "traffic": traffic / 1e9,
+            "scope": "one IMEX stage 2 (ghost fill, x/y/z flux sweeps, update + recovery) at the median time",
+            "algorithmic_bytes_per_zone": STAGE_FLOOR_BYTES, "algorithmic_GB": nbytes / 1e9,
+            "traffic_unit": "GB per stage (FETCH_SIZE + WRITE_SIZE of the four launches, calibrated)",
+            "traffic_over_algorithmic": traffic / nbytes,
+            "fp64": {"flops_per_zone_counted": sum(FLOPS_PER_CELL.values()), "TFLOP": flops / 1e12,
+                     "achieved_TFLOPs": flops / t / 1e12, "peak_TFLOPs": PEAK_FP64_VECTOR_TFLOPS,
+                     "frac": flops / t / 1e12 / PEAK_FP64_VECTOR_TFLOPS},
+            "ceilings_ms": {"hbm": t_hbm * 1e3, "fp64": t_alu * 1e3},
+            "min_roofline_frac": max(t_hbm, t_alu) / t}
+    br = {}
+    for k, kms in kernels_ms.items():
+        if k not in FLOPS_PER_CELL or kms <= 0:
+            continue
+        tk = kms * 1e-3
+        b = BYTES_PER_CELL[k] * ncell
+        f = FLOPS_PER_CELL[k] * ncell
+        tb = max(b / (PEAK_HBM_GBS * 1e9), f / (PEAK_FP64_VECTOR_TFLOPS * 1e12))
+        br[k] = {"ms": kms, "design_GB": b / 1e9, "hbm_frac": b / tk / 1e9 / PEAK_HBM_GBS,
+                 "fp64_frac": f / tk / 1e12 / PEAK_FP64_VECTOR_TFLOPS, "roofline_frac": tb / tk,
+                 "traffic_GB": TRAFFIC_BYTES_PER_CELL[k] * ncell / 1e9}
+    roof["kernels"] = br
     return roof
+
+
+def subbox(t, off, lo, size):
+    """host copy of t[..., box with 3 ghost cells] of a device tensor in a
+    grid's layout; lo and size per axis (x, y, z) in interior cells"""
+    oz, oy, ox = off
+    sl = (slice(lo[2] + oz, lo[2] + oz + size[2] + 6), slice(lo[1] + oy, lo[1] + oy + size[1] + 6),
+          slice(lo[0] + ox, lo[0] + ox + size[0] + 6))
+    return np.ascontiguousarray(t[(Ellipsis,) + sl].cpu().numpy())
+
+
+def oracle_on_state(oracle, w, dt, U, P, off, size, reps):
+    """`reps` oracle stage-2 applications on the central box of the GPU's
+    state (U, P in the grid's layout): the real neighbours as ghost cells,
+    held fixed; stage 1 first, as on the GPU.  Returns (seconds, cells,
+    failed cells)."""
+    N = w.n[0]
+    lo = [N // 2 - s // 2 for s in size]
+    Us = subbox(U, off, lo, size)
+    Ps = subbox(P, off, lo, size)
+    sl = tuple(slice(lo[d], lo[d] + size[d] + 6) for d in (2, 1, 0))
+    met = np.ascontiguousarray(w.metric[(slice(None),) + sl])
+    sig = np.ascontiguousarray(w.sigma[sl])
+    x0 = tuple(w.x0[d] + lo[d] * w.dx[d] for d in range(3))
+    og = oracle.make_grid(tuple(size), 7, w.dx, (oracle.BC_GIVEN,) * 3, w.gamma_ad, recon=w.recon, x0=x0)
+    s1 = oracle.stage1(og, dt, sig, Us, Ps, met)
+    t0 = time.perf_counter()
+    nf = 0
+    for _ in range(reps):
+        s2 = oracle.stage2(og, dt, sig, Us, s1["P1"], s1["R1"], met)
+        nf += int(s2["nfail"])
+    return time.perf_counter() - t0, size[0] * size[1] * size[2] * reps, nf
+
+
+def cpu_baseline(oracle, w, dt, U, P, off, sample, reps, single):
+    """The oracle, as it stands, on the state the GPU times: the central
+    sample box of the 256^3 state after the evolution steps, all host
+    threads, then one thread on a smaller central box."""
+    t, cells, nf = oracle_on_state(oracle, w, dt, U, P, off, sample, reps)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    t1, cells1, nf1 = oracle_on_state(oracle, w, dt, U, P, off, single, 1)
+    oracle.set_num_threads(threads)
+    return {"value": cells / t, "unit": "zone-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} applications of IMEX stage 2 on the central {'x'.join(map(str, sample))} cells "
+                      f"of the GPU's timed state (256^3 curved blob after the evolution steps; real neighbours "
+                      f"as ghost cells, held fixed): {t:.2f} s, {nf} failed cells",
+            "cpu_model": cpu_model(), "threads": threads,
+            "single_thread": {"value": cells1 / t1, "unit": "zone-updates/s",
+                              "sample": f"one stage-2 application on the central {'x'.join(map(str, single))} "
+                                        f"cells of the same state: {t1:.2f} s, {nf1} failed cells"}}
 
 
 def adjoint_leg(torch, rmhd, W, steps):
@@ -181,6 +259,116 @@ def adjoint_leg(torch, rmhd, W, steps):
             "fwd_adjoint_s_per_step": t_fb / steps, "fwd_s_per_step": t_f / steps,
             "adjoint_over_forward": (t_fb - t_f) / t_f, "loss": float(L),
             "grad_norm_By0": float(gB.norm()), "grad_norm_log_sigma": float(gs.norm())}
+
+
+def other_configs(torch, rmhd, W, oracle):
+    """GPU and oracle timings of the smaller workloads: the nine 400-cell
+    shocktubes (320 steps each), the 128^3 periodic box (10 steps on the GPU,
+    one on the oracle) and the 64 x 2048 batch forward (and the oracle's
+    forward-mode tangent)."""
+    out = {}
+    # shocktubes: the GPU runs all nine, the oracle one seed per sigma
+    t_gpu, zs = 0.0, 0
+    runs = []
+    for seed in (101, 102, 103):
+        for s0 in (1.0, 1e3, 1e6):
+            w = W.shocktube(seed=seed, sigma0=s0)
+            g = rmhd.grid_for(w)
+            sig = torch.from_numpy(w.sigma).cuda()
+            P = torch.from_numpy(w.P).cuda()
+            U = g.prim2con(P)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(w.steps):
+                g.step(w.dt, sig, U, P)
+            torch.cuda.synchronize()
+            t_gpu += time.perf_counter() - t0
+            zs += 2 * w.steps * w.n_interior
+            if g.failures():
+                raise SystemExit(f"recovery failures in the shocktube seed {seed} sigma {s0}")
+            runs.append((seed, s0))
+    t_orc, zo = 0.0, 0
+    if oracle is not None:
+        for s0 in (1.0, 1e3, 1e6):
+            w = W.shocktube(seed=101, sigma0=s0)
+            og = oracle.make_grid(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=w.recon, x0=w.x0)
+            P = w.P.copy()
+            U = oracle.prim2con(og, P)
+            t0 = time.perf_counter()
+            for _ in range(w.steps):
+                oracle.step(og, w.dt, w.sigma, U, P)
+            t_orc += time.perf_counter() - t0
+            zo += 2 * w.steps * w.n_interior
+    out["shocktube_400"] = {
+        "workload": "nine 400-cell resistive shocktubes (seeds 101-103 x sigma 1, 1e3, 1e6), minmod, 320 steps "
+                    "each to t = 0.4 (one launch sequence per step: latency-bound on the GPU)",
+        "gpu": {"value": zs / t_gpu, "unit": "zone-updates/s per stage", "s_per_run": t_gpu / len(runs)},
+        "oracle": None if oracle is None else {"value": zo / t_orc, "unit": "zone-updates/s per stage",
+                                               "s_per_run": t_orc / 3, "runs": "seed 101, sigma 1, 1e3, 1e6"}}
+    log(f"shocktubes: GPU {zs / t_gpu:.3g}, oracle {zo / max(t_orc, 1e-9):.3g} zone-updates/s per stage")
+
+    # periodic box 128^3
+    w = W.periodic_box(n=128)
+    g = rmhd.grid_for(w, x_align=1)
+    sig = g.to_layout(w.sigma)
+    P = g.to_layout(w.P)
+    U = g.prim2con(P)
+    per, _ = timed_calls(torch, lambda: g.step(w.dt, sig, U, P), w.steps, 0)
+    if g.failures():
+        raise SystemExit("recovery failures in the periodic box")
+    ms_step = statistics.median(per)
+    box = {"workload": f"{w.name}: 128^3 flat periodic, WENO5, {w.steps} IMEX steps (median step)",
+           "gpu": {"value": 2 * w.n_interior / (ms_step * 1e-3), "unit": "zone-updates/s per stage",
+                   "ms_per_step": ms_step}}
+    del g, U, P, sig
+    if oracle is not None:
+        og = oracle.make_grid(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=w.recon, x0=w.x0)
+        Po = w.P.copy()
+        Uo = oracle.prim2con(og, Po)
+        t0 = time.perf_counter()
+        oracle.step(og, w.dt, w.sigma, Uo, Po)
+        t = time.perf_counter() - t0
+        box["oracle"] = {"value": 2 * w.n_interior / t, "unit": "zone-updates/s per stage", "s_per_step": t,
+                         "sample": "the first IMEX step"}
+    out["periodic_box_128"] = box
+    log(f"periodic box: GPU {box['gpu']['value']:.3g} zone-updates/s per stage")
+
+    # 64 x 2048 batch forward
+    w = W.sheet_batch()
+    g = rmhd.grid_for(w)
+    sig = torch.from_numpy(w.sigma).cuda()
+    P = torch.from_numpy(w.P).cuda()
+    U = g.prim2con(P)
+    per, tot = timed_calls(torch, lambda: g.step(w.dt, sig, U, P), 40, 0)
+    batch = {"workload": "64 x 2048 current-sheet batch, WENO5, forward steps",
+             "gpu": {"s_per_step": statistics.median(per) * 1e-3,
+                     "value": 2 * w.n_interior / (statistics.median(per) * 1e-3),
+                     "unit": "zone-updates/s per stage"}}
+    del g, U, P, sig
+    if oracle is not None:
+        og = oracle.make_grid(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=w.recon, x0=w.x0)
+        Po = w.P.copy()
+        Uo = oracle.prim2con(og, Po)
+        nst = 10
+        t0 = time.perf_counter()
+        for _ in range(nst):
+            oracle.step(og, w.dt, w.sigma, Uo, Po)
+        t_f = (time.perf_counter() - t0) / nst
+        rng = np.random.default_rng(7)
+        dU = rng.standard_normal(Uo.shape)
+        ds = rng.standard_normal(w.sigma.shape)
+        ntan = 3
+        t0 = time.perf_counter()
+        for _ in range(ntan):
+            oracle.step_tangent(og, w.dt, w.sigma, Uo, dU, Po, dsigma=ds)
+        t_t = (time.perf_counter() - t0) / ntan
+        batch["oracle"] = {"s_per_step": t_f, "tangent_s_per_step": t_t,
+                           "value": 2 * w.n_interior / t_f, "unit": "zone-updates/s per stage",
+                           "sample": f"{nst} forward steps, then {ntan} steps in dual numbers (forward-mode "
+                                     f"tangent along a random (U, sigma) direction)"}
+    out["sheet_batch_64x2048"] = batch
+    log(f"batch: GPU {batch['gpu']['s_per_step'] * 1e3:.3f} ms per forward step")
+    return out
 
 
 def main():
@@ -233,10 +421,10 @@ def main():
         if nfail:
             raise SystemExit("recovery failures during evolution")
 
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-
-    def time_stage2(g, U, P, steps, warmup):
-        """K timed applications of IMEX stage 2 at the state (U, P)"""
+    def time_stage2(g, U, P, steps, warmup, breakdown):
+        """K applications of IMEX stage 2 at the state (U, P), each timed by
+        events with the launch timers off; then (optionally) K more with the
+        library's per-launch timers on for the per-kernel breakdown"""
         P1, R1 = g.empty(), g.empty(3)
         g.imex_stage(1, dt, sig, U, P, P1, R_out=R1)
         U2, P2, R2 = g.empty(), g.empty(), g.empty(3)
@@ -244,20 +432,15 @@ def main():
         def stage2():
             g.imex_stage(2, dt, sig, U, P1, P2, R_out=R2, R1=R1, U_out=U2)
 
-        for _ in range(warmup):
-            stage2()
-        torch.cuda.synchronize()
-        g.timing(True)
-        g.timing_read()
-        torch.cuda.synchronize()
-        start.record()
-        for _ in range(steps):
-            stage2()
-        stop.record()
-        torch.cuda.synchronize()
-        ms = start.elapsed_time(stop)
-        kern = g.timing_read()
-        g.timing(False)
+        per, tot = timed_calls(torch, stage2, steps, warmup)
+        kern = None
+        if breakdown:
+            g.timing(True)
+            g.timing_read()
+            for _ in range(steps):
+                stage2()
+            kern = g.timing_read()
+            g.timing(False)
         # one more application, untimed, for the recovery iteration histogram
         g.recovery_stats(True)
         stage2()
@@ -267,24 +450,34 @@ def main():
         if nfail:
             raise SystemExit(f"{nfail} failed recoveries in the timed stages")
         del P1, R1, U2, P2, R2
-        return ms, kern, {str(i): c for i, c in enumerate(hist) if c}
+        return per, tot, kern, {str(i): c for i, c in enumerate(hist) if c}
 
     evolve(g, U, P, args.evolve, "fp64")
-    ms, kern, hist = time_stage2(g, U, P, args.steps, args.warmup)
-    value = ncell * args.steps / (ms * 1e-3)
-    log(f"stage 2: {ms / args.steps:.3f} ms -> {value:.4g} zone-updates/s")
+    per, tot, kern, hist = time_stage2(g, U, P, args.steps, args.warmup, not args.no_breakdown)
+    ms = statistics.median(per)
+    value = ncell / (ms * 1e-3)
+    log(f"stage 2: median {ms:.3f} ms (mean {tot / args.steps:.3f}, min {min(per):.3f}, max {max(per):.3f}) -> "
+        f"{value:.4g} zone-updates/s")
+    per_launch = {} if kern is None else {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t0 = time.perf_counter()
+        cpu = cpu_baseline(oracle, w, dt, U, P, rmhd.std_offsets(g.desc),
+                           tuple(int(x) for x in args.cpu_sample.split(",")), args.cpu_reps,
+                           tuple(int(x) for x in args.cpu_single.split(",")))
+        log(f"cpu baseline {cpu['value']:.4g} zone-updates/s ({cpu['threads']} threads), single thread "
+            f"{cpu['single_thread']['value']:.4g}, in {time.perf_counter() - t0:.1f} s")
 
     # full IMEX steps (stage 1 + stage 2 + final), reported beside
     Uc, Pc = U.clone(), P.clone()
-    torch.cuda.synchronize()
-    start.record()
-    for _ in range(args.full_steps):
-        g.step(dt, sig, Uc, Pc)
-    stop.record()
-    torch.cuda.synchronize()
-    ms_step = start.elapsed_time(stop) / max(1, args.full_steps)
+    per_step, _ = timed_calls(torch, lambda: g.step(dt, sig, Uc, Pc), args.full_steps, 0)
+    ms_step = statistics.median(per_step)
     if g.failures():
         raise SystemExit("failed recoveries in the full steps")
+    del Uc, Pc
 
     if args.calibrate_copy:
         # a plain streaming kernel of known traffic for the HBM byte counters:
@@ -301,69 +494,68 @@ def main():
     if not args.no_other_recon:
         orec = "mc2" if args.recon == "weno5" else "weno5"
         go, _, _ = setup("fp64", orec)
-        ms_o, kern_o, _ = time_stage2(go, U, P, args.steps, args.warmup)
-        other = {"recon": orec, "value": ncell * args.steps / (ms_o * 1e-3), "unit": "zone-updates/s",
-                 "ms_per_step": ms_o / args.steps,
-                 "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern_o.items()}}
-        log(f"{orec} stage 2 on the same state: {ms_o / args.steps:.3f} ms")
+        per_o, _, _, _ = time_stage2(go, U, P, args.steps, args.warmup, False)
+        ms_o = statistics.median(per_o)
+        other = {"recon": orec, "value": ncell / (ms_o * 1e-3), "unit": "zone-updates/s", "ms_per_step": ms_o}
+        log(f"{orec} stage 2 on the same state: {ms_o:.3f} ms")
         del go
 
     mixed = None
     if not args.no_mixed:
         gm, Um, Pm = setup("mixed")
         evolve(gm, Um, Pm, args.evolve, "mixed")
-        ms_m, kern_m, _ = time_stage2(gm, Um, Pm, args.steps, args.warmup)
-        val_m = ncell * args.steps / (ms_m * 1e-3)
-        log(f"mixed stage 2: {ms_m / args.steps:.3f} ms -> {val_m:.4g} zone-updates/s")
+        per_m, _, kern_m, _ = time_stage2(gm, Um, Pm, args.steps, args.warmup, not args.no_breakdown)
+        ms_m = statistics.median(per_m)
+        val_m = ncell / (ms_m * 1e-3)
+        log(f"mixed stage 2: {ms_m:.3f} ms -> {val_m:.4g} zone-updates/s")
         # accuracy: both forms from the same seed to the same step count
         rest = max(0, args.mixed_steps - args.evolve)
-        evolve(g, U, P, rest, "fp64 accuracy run")
+        Ua, Pa = U.clone(), P.clone()
+        evolve(g, Ua, Pa, rest, "fp64 accuracy run")
         evolve(gm, Um, Pm, rest, "mixed accuracy run")
         I = (slice(None),) + tuple(w.interior)
-        P, Pm = g.from_layout(P), gm.from_layout(Pm)     # the 3-ghost layout of w.interior
+        Pa, Pm = g.from_layout(Pa), gm.from_layout(Pm)     # the 3-ghost layout of w.interior
         names = ["rho", "p", "vx", "vy", "vz", "Bx", "By", "Bz", "Ex", "Ey", "Ez", "phi", "psi", "q"]
         errs = {}
         # E (slaved to -v x B in the stiff interior) is measured against the
         # electromagnetic scale max(|E|, |B|), as are phi, psi and q
-        em_max = float(P[5:11][I].abs().max())
-        em_sum = max(float(P[f][I[1:]].abs().sum()) for f in range(5, 11))
+        em_max = float(Pa[5:11][I].abs().max())
+        em_sum = max(float(Pa[f][I[1:]].abs().sum()) for f in range(5, 11))
         for f, nm in enumerate(names):
-            a, b = P[f][I[1:]], Pm[f][I[1:]]
+            a, b = Pa[f][I[1:]], Pm[f][I[1:]]
             d = (a - b).abs()
             s1, si = float(a.abs().sum()), float(a.abs().max())
             if f >= 8:
                 s1, si = max(s1, em_sum), max(si, em_max)
             errs[nm] = {"L1": float(d.sum()) / max(s1, 1e-300), "Linf": float(d.max()) / max(si, 1e-300)}
         worst = max(max(errs[n]["L1"], errs[n]["Linf"]) for n in ["rho", "p", "Bx", "By", "Bz", "Ex", "Ey", "Ez"])
-        mixed = {"value": val_m, "unit": "zone-updates/s", "ms_per_step": ms_m / args.steps,
+        mixed = {"value": val_m, "unit": "zone-updates/s", "ms_per_step": ms_m,
                  "speedup_vs_fp64": ms / ms_m,
-                 "kernels_ms_per_launch": {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern_m.items()},
+                 "kernels_ms_per_launch": None if kern_m is None else
+                 {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern_m.items()},
                  "accuracy_steps": args.evolve + rest,
                  "max_rel_err_rho_p_B_E": worst, "per_field_vs_fp64": errs,
                  "reference": "the FP64 GPU path from the same seed (equal to the oracle by the parity tests)"}
         log(f"mixed: speedup {ms / ms_m:.3f}, max rel err (rho, p, B, E) after {args.evolve + rest} steps "
             f"{worst:.3e}")
-        del gm, Um, Pm
+        del gm, Um, Pm, Ua, Pa
+
+    del g, U, P
+    met = sig = None
+    torch.cuda.empty_cache()
 
     adjoint = None
     if not args.no_adjoint:
         adjoint = adjoint_leg(torch, rmhd, W, args.adjoint_steps)
 
-    per_launch = {k: (v[0] / v[1] if v[1] else 0.0) for k, v in kern.items()}
-    roof = roofline(per_launch, kern, ncell)
-    stage_bytes = sum(BYTES_PER_CELL.get(k, 0) * kern[k][1] for k in kern) / max(1, args.steps) * ncell
-    stage_flops = sum(FLOPS_PER_CELL.get(k, 0.0) * kern[k][1] for k in kern) / max(1, args.steps) * ncell
-    roof["stage"] = {"ms": ms / args.steps, "algorithmic_GB": stage_bytes / 1e9,
-                     "hbm_frac": stage_bytes / (ms / args.steps * 1e-3) / 1e9 / PEAK_HBM_GBS,
-                     "fp64_TFLOP": stage_flops / 1e12,
-                     "fp64_frac": stage_flops / (ms / args.steps * 1e-3) / 1e12 / PEAK_FP64_VECTOR_TFLOPS}
+    configs = None
+    if not args.no_configs:
+        orc = None
+        if not args.no_cpu_baseline:
+            import oracle as orc
+        configs = other_configs(torch, rmhd, W, orc)
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        del U, P, Uc, Pc
-        t0 = time.perf_counter()
-        cpu = cpu_baseline(w, dt, tuple(int(x) for x in args.cpu_sample.split(",")), args.cpu_reps)
-        log(f"cpu baseline {cpu['value']:.4g} zone-updates/s in {time.perf_counter() - t0:.1f} s")
+    roof = stage_roofline(ms, ncell, per_launch)
 
     out = {
         "metric": METRIC,
@@ -372,7 +564,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms / args.steps,
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -382,6 +574,8 @@ def main():
                                f"{args.evolve} steps (static conformally flat metric, Gamma = 2, "
                                f"sigma = 1e6 rho/rho_max + 1, CFL 0.25, copy boundaries)",
                    "n": [args.n] * 3, "recon": args.recon, "dt": dt, "parallelism": "single GPU"},
+        "timing": {"statistic": "median of the per-application event times", "ms_median": ms,
+                   "ms_mean": tot / args.steps, "ms_min": min(per), "ms_max": max(per)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "kernels_ms_per_launch": per_launch,
@@ -390,6 +584,7 @@ def main():
         "other_recon": other,
         "mixed": mixed,
         "adjoint": adjoint,
+        "configs": configs,
     }
     print(json.dumps(out))
     return 0
