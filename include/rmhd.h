@@ -179,8 +179,8 @@ size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc);
  * cell whose recovery Jacobian is singular at the root has no implicit-
  * function derivative: its multiplier is set to zero and the cell is counted
  * by rmhd_failures() (as are failed recoveries of the recomputed forward
- * stages), so a caller that finds a nonzero count must not trust the
- * gradient. */
+ * stages and cells whose sensitivities come out non-finite), so a caller
+ * that finds a nonzero count must not trust the gradient. */
 int rmhd_step_adjoint(rmhd_ctx* ctx, double dt, const double* sigma, const double* U_n, const double* P_n,
                       const double* Ubar_np1, double* Ubar_n, double* sigma_bar, void* adj_ws, size_t adj_bytes);
 

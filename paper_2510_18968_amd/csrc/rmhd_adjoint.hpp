@@ -485,6 +485,12 @@ __global__ __launch_bounds__(128) void k_adj_point(const Params p, double dt, co
         for (int f = 0; f < NF; ++f) Ubn[f * Np + o] += Yb[f];
     }
     sb[o] += thb[14];
+    // a non-finite sensitivity (from this cell or carried in by Pb, e.g. at a
+    // state so close to the light cone that its derivatives overflow) is
+    // counted with the failures, never passed on silently
+    bool finite = isfinite(thb[14]);
+    for (int f = 0; f < NF; ++f) finite = finite && isfinite(Yb[f]);
+    if (!finite) atomicAdd(nfail, 1ull);
 }
 
 __global__ __launch_bounds__(256) void k_adj_sigma_out(const Params p, const double* __restrict__ sb,
