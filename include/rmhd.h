@@ -184,6 +184,25 @@ size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc);
 int rmhd_step_adjoint(rmhd_ctx* ctx, double dt, const double* sigma, const double* U_n, const double* P_n,
                       const double* Ubar_np1, double* Ubar_n, double* sigma_bar, void* adj_ws, size_t adj_bytes);
 
+/* rmhd_step_adjoint without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, kernels and results as
+ * rmhd_step_adjoint; its 79-field scratch is instead a static device array of
+ * RMHD_STATIC_SCRATCH_BYTES (one copy per device, reserved when the library
+ * loads on that device and held until the process ends; its address is
+ * resolved once per device by rmhd_init_grid).  Allocates nothing.  Returns
+ * RMHD_EINVAL if the grid needs more than RMHD_STATIC_SCRATCH_BYTES (that is
+ * rmhd_adjoint_workspace_bytes(desc) > RMHD_STATIC_SCRATCH_BYTES: about
+ * 212,000 padded cells, e.g. the 64 x 2048 batch) or if launch timing is on
+ * (its events allocate); RMHD_EHIP if the array's address could not be
+ * resolved.  Every call on one device shares the array and leaves its
+ * contents behind (the parts that must start at zero are cleared inside each
+ * call): calls that overlap on one device, on any streams or contexts, race
+ * and must be ordered by the caller. */
+#define RMHD_STATIC_SCRATCH_BYTES (128u * 1024u * 1024u)
+int rmhd_step_adjoint_static(rmhd_ctx* ctx, double dt, const double* sigma, const double* U_n,
+                             const double* P_n, const double* Ubar_np1, double* Ubar_n, double* sigma_bar);
+
 /* Adjoint of rmhd_prim2con at the primitives P: Pbar = (dU/dP)^T Ubar at
  * interior cells (eqs. conserved_dens, conserved_tau, conserved_S). */
 int rmhd_prim2con_adjoint(rmhd_ctx* ctx, const double* P, const double* Ubar, double* Pbar);

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -25,6 +26,9 @@ struct rmhd_ctx {
                                     // [3] dummy status word;
                                     // [32..127] recovery iteration histograms
     bool curved;
+    int device = 0;                 // the device current at rmhd_init_grid
+    void* scratch = nullptr;        // that device's copy of the static adjoint scratch (or null)
+    std::string scratch_err;        // why it could not be resolved
     long persist_blocks = 256;   // persistent flux grid: one 4-wave block per CU, multiple of 8
     // opt-in launch timing: event pairs per kernel class, reused after a read
     bool timing = false;
@@ -32,6 +36,11 @@ struct rmhd_ctx {
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev[RMHD_TIMING_CLASSES];
     size_t used[RMHD_TIMING_CLASSES] = {};
 };
+
+// Scratch of rmhd_step_adjoint_static: the adjoint workspace for callers that
+// cannot allocate device memory.  One copy per device, held until the process
+// ends; every call on a device shares it.
+__device__ __align__(256) char scratch[RMHD_STATIC_SCRATCH_BYTES];
 
 namespace {
 
@@ -56,6 +65,16 @@ int fail(int code, const std::string& msg) {
 
 constexpr size_t ALIGN = 256;
 size_t up(size_t b) { return (b + ALIGN - 1) / ALIGN * ALIGN; }
+
+// Device addresses of the static adjoint scratch, one per device (each device
+// holds its own copy of the array, at its own address).  In host code the
+// array's name is only a host-side stand-in, so kernels get these addresses.
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[MAX_DEVICES] = {};
+
+// the address of `scratch` on device dev, which must be the current device
+int resolve_scratch(int dev, void** out, std::string& why);
 
 // padding on each side of dimension k: the ghost width on active dimensions,
 // X_ALIGN_PAD along an active x with x_align (interior rows on 128-byte lines)
@@ -368,6 +387,26 @@ int fill(rmhd_ctx* c, double* a, long n) {
     return RMHD_OK;
 }
 
+int resolve_scratch(int dev, void** out, std::string& why) {
+    *out = nullptr;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        why = "device ordinal " + std::to_string(dev) + " beyond the static scratch table";
+        return RMHD_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void* a = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a) {
+            why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return RMHD_EHIP;
+        }
+        g_scratch_addr[dev] = a;
+    }
+    *out = g_scratch_addr[dev];
+    return RMHD_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -419,6 +458,24 @@ int rmhd_step_adjoint(rmhd_ctx* c, double dt, const double* sigma, const double*
     k_adj_sigma_out<<<nblk(n, 256), 256, 0, c->stream>>>(c->p, sb, sigma_bar);
     LAUNCH_CHECK();
     return RMHD_OK;
+}
+
+int rmhd_step_adjoint_static(rmhd_ctx* c, double dt, const double* sigma, const double* U_n, const double* P_n,
+                             const double* Ubar_np1, double* Ubar_n, double* sigma_bar) {
+    if (!c) return fail(RMHD_EINVAL, "null context");
+    // the launch timers create events, which allocate
+    if (c->timing) return fail(RMHD_EINVAL, "rmhd_step_adjoint_static: switch the launch timing off first");
+    const size_t need = rmhd_adjoint_workspace_bytes(&c->desc);
+    if (need == 0) return fail(RMHD_EINVAL, "invalid grid");
+    if (need > (size_t)RMHD_STATIC_SCRATCH_BYTES)
+        return fail(RMHD_EINVAL, "rmhd_step_adjoint_static: this grid needs " + std::to_string(need) +
+                                     " bytes of adjoint scratch; the static scratch holds " +
+                                     std::to_string((size_t)RMHD_STATIC_SCRATCH_BYTES));
+    if (!c->scratch)
+        return fail(RMHD_EHIP, "rmhd_step_adjoint_static: no static scratch on this device: " + c->scratch_err);
+    // the kernels take the device address resolved at rmhd_init_grid; the
+    // buffers that must start at zero are cleared by fill kernels inside
+    return rmhd_step_adjoint(c, dt, sigma, U_n, P_n, Ubar_np1, Ubar_n, sigma_bar, c->scratch, need);
 }
 
 int rmhd_prim2con_adjoint(rmhd_ctx* c, const double* P, const double* Ubar, double* Pbar) {
@@ -497,9 +554,16 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     c->curved = false;
     {
         int dev = 0, cus = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
-            c->persist_blocks = ((long)cus + 7) / 8 * 8;
+        if (hipGetDevice(&dev) == hipSuccess) {
+            c->device = dev;
+            if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+                c->persist_blocks = ((long)cus + 7) / 8 * 8;
+            // the static adjoint scratch of this device (once per device); a
+            // failure only disables rmhd_step_adjoint_static on this context
+            if (resolve_scratch(dev, &c->scratch, c->scratch_err) != RMHD_OK) c->scratch = nullptr;
+        } else {
+            c->scratch_err = "hipGetDevice failed at rmhd_init_grid";
+        }
     }
     k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 2);
     hipError_t e = hipGetLastError();

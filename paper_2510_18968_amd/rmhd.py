@@ -22,7 +22,8 @@ PREC = {"fp64": 0, "mixed": 1}
 SYMBOLS = ("rmhd_workspace_bytes", "rmhd_padded_extent", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
            "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
-           "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read", "rmhd_set_stream")
+           "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read", "rmhd_set_stream",
+           "rmhd_step_adjoint_static")
 HIST_BINS = 32
 TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
 
@@ -73,6 +74,7 @@ def lib() -> C.CDLL:
             "rmhd_timing_read": (C.c_int, [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
             "rmhd_adjoint_workspace_bytes": (C.c_size_t, [gp]),
             "rmhd_step_adjoint": (C.c_int, [vp, C.c_double, vp, vp, vp, vp, vp, vp, vp, C.c_size_t]),
+            "rmhd_step_adjoint_static": (C.c_int, [vp, C.c_double, vp, vp, vp, vp, vp, vp]),
             "rmhd_prim2con_adjoint": (C.c_int, [vp, vp, vp, vp]),
             "rmhd_recovery_stats": (C.c_int, [vp, C.c_int]),
             "rmhd_recovery_stats_read": (C.c_int, [vp, C.POINTER(C.c_int64)]),
@@ -264,6 +266,14 @@ class Grid:
                                        self._ptr(P_n, 14), self._ptr(Ubar_np1, 14), self._ptr(Ubar_n, 14),
                                        self._ptr(sigma_bar), C.c_void_p(self._adj_ptr), self._adj_bytes),
                "rmhd_step_adjoint")
+
+    def step_adjoint_static(self, dt, sigma, U_n, P_n, Ubar_np1, Ubar_n, sigma_bar):
+        """step_adjoint with the library's static per-device scratch instead
+        of a workspace (allocates nothing; calls on one device must not
+        overlap)."""
+        _check(lib().rmhd_step_adjoint_static(self._ctx, float(dt), self._ptr(sigma), self._ptr(U_n, 14),
+                                              self._ptr(P_n, 14), self._ptr(Ubar_np1, 14), self._ptr(Ubar_n, 14),
+                                              self._ptr(sigma_bar)), "rmhd_step_adjoint_static")
 
     def prim2con_adjoint(self, P, Ubar, Pbar=None):
         Pbar = self.empty() if Pbar is None else Pbar
