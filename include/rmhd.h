@@ -66,7 +66,8 @@ enum rmhd_status {
     RMHD_EUNPHYS = -4   /* per-cell: unphysical state (rho<=0, v^2>=1, NaN ..) */
 };
 /* per-cell status values written by the recovery: 0 ok, 1 converged at the
- * iteration cap within 1e-12 (warning), RMHD_ENOCONV, RMHD_EUNPHYS */
+ * iteration cap within 1e-12 (warning), 2 (RMHD_ST_ATMO) atmosphere state
+ * set at the end of the step, RMHD_ENOCONV, RMHD_EUNPHYS */
 
 enum rmhd_recon { RMHD_RECON_MINMOD = 0, RMHD_RECON_MC2 = 1, RMHD_RECON_WENO5 = 2 };
 enum rmhd_bc { RMHD_BC_PERIODIC = 0, RMHD_BC_COPY = 1 };
@@ -91,7 +92,32 @@ typedef struct {
     double gamma_ad;     /* ideal-gas adiabatic index Gamma (Sec. III.B)        */
     double kappa;        /* divergence-cleaning damping (1 in the paper, Sec. IV)*/
     double c2p_tol;      /* recovery tolerance on |dp|/p and |dv| (1e-14)       */
+    /* conductivity (Sec. IV.A, IV.E): RMHD_SIGMA_FIELD takes the caller's
+       per-cell sigma array; the models set sigma from the conserved D of the
+       state each use acts on -- the stage's explicit state in an implicit
+       solve (the solve leaves D unchanged), sqrt(gamma) rho W of the stage
+       primitives at every cell centre in the charge flux -- and the sigma
+       argument of the stage calls is then ignored (may be NULL)           */
+    int32_t sigma_model; /* enum rmhd_sigma_model                              */
+    int32_t reserved_;   /* set to 0                                           */
+    double sigma0;       /* sigma_0 of both models                              */
+    double sigma_exp;    /* gamma of eq. sigma_evol                             */
+    double sigma_Datmo;  /* D_atmo of eq. dynamo_sigma                          */
+    /* artificial atmosphere (Sec. IV.E), off when rho_atmo = 0: at the end of
+       each step (the final update) a cell whose assembled D is below
+       RMHD_ATMO_FACTOR sqrt(gamma) rho_atmo gets the D, S_i and tau of the
+       state rho = rho_atmo, v = 0, p = K_atmo rho_atmo^Gamma with its own E,
+       B and cleaning fields, is recovered from it and flagged with status
+       RMHD_ST_ATMO (counted by rmhd_atmosphere_cells, not a failure)      */
+    double rho_atmo;
+    double K_atmo;
 } rmhd_grid_desc;
+
+/* sigma = field | sigma0 D^sigma_exp (eq. sigma_evol) |
+ * sigma0 max(1 - sigma_Datmo / D, 0)^2 (eq. dynamo_sigma) */
+enum rmhd_sigma_model { RMHD_SIGMA_FIELD = 0, RMHD_SIGMA_POWER = 1, RMHD_SIGMA_DYNAMO = 2 };
+#define RMHD_ATMO_FACTOR 1.01
+#define RMHD_ST_ATMO 2
 
 /* Buffers of one IMEX stage (Sec. III.A, eq. IMEX3).  [3][Np] arrays hold the
  * stiff E source R_E of a stage, recovered from the stage equation as
@@ -154,7 +180,8 @@ int rmhd_prim2con(rmhd_ctx* ctx, const double* P, double* U);
 int rmhd_con2prim(rmhd_ctx* ctx, const double* U, double* P, int32_t* status);
 
 /* One stage of IMEX-SSP2(2,2,2) (table imex, eq. IMEX3), see rmhd_stage_bufs.
- * sigma: conductivity [Np] (ghost cells are not read). */
+ * sigma: conductivity [Np] (ghost cells are not read; ignored, may be NULL,
+ * when the descriptor selects a conductivity model). */
 int rmhd_imex_stage(rmhd_ctx* ctx, int stage, double dt, const double* sigma, const rmhd_stage_bufs* bufs);
 
 /* One full IMEX-SSP2(2,2,2) step in place: (U, P) at t -> t + dt.  Stage
@@ -175,7 +202,9 @@ size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc);
  * their local Jacobians, the stage combination of eq. IMEX3 exactly; limiter
  * kinks and first-order fallbacks take the derivative of the branch taken.
  * Ubar_n may alias Ubar_np1.  adj_ws: >= rmhd_adjoint_workspace_bytes bytes,
- * 256-byte aligned.  Returns RMHD_EINVAL for the mixed-precision form.  A
+ * 256-byte aligned.  Returns RMHD_EINVAL for the mixed-precision form and
+ * for a conductivity model or an atmosphere (it differentiates the static
+ * sigma field without floors).  A
  * cell whose recovery Jacobian is singular at the root has no implicit-
  * function derivative: its multiplier is set to zero and the cell is counted
  * by rmhd_failures() (as are failed recoveries of the recomputed forward
@@ -215,6 +244,11 @@ int rmhd_max_signal_speed(rmhd_ctx* ctx, double* host_out);
 /* Number of failed per-cell recoveries since the last call (then reset).
  * Synchronises the stream. */
 int rmhd_failures(rmhd_ctx* ctx, int64_t* host_out);
+
+/* Number of cells set to the atmosphere state (rho_atmo > 0, Sec. IV.E) by
+ * the final updates since the last call (then reset).  Synchronises the
+ * stream. */
+int rmhd_atmosphere_cells(rmhd_ctx* ctx, int64_t* host_out);
 
 /* Opt-in histograms of recovery iterations (diagnostic, off by default; the
  * cost of a recovery follows its iteration count, Sec. III.B).  With enable

@@ -47,8 +47,9 @@
  *   - a conductivity model sigma(D) takes the conserved D of the state it
  *     acts on: in an implicit solve the D of the stage's explicit state (the
  *     solve does not change D); in the charge flux of F(U(s)) the D of the
- *     stage primitives at each cell centre (sqrt(gamma) rho W, ghost cells
- *     included);
+ *     stage primitives at each cell centre (sqrt(gamma) rho W); a ghost cell
+ *     holds a copy of its interior image and carries the image's sigma, as
+ *     the given sigma field does;
  *   - the artificial atmosphere acts at the end of each step: a cell whose
  *     assembled D is below 1.01 sqrt(gamma) rho_atmo gets the hydro part
  *     (D, S_i, tau) of the atmosphere state (rho_atmo, p = K_atmo
@@ -975,6 +976,29 @@ template <class T>
 void explicit_rhs(const Grid& gr, const Geo& ge, const T* metric, const T* Pst, const T* sig, T* L) {
     const long Np = ge.Np;
     const double G = gr.gamma_ad;
+    /* conductivity of each cell: the given field, or the model at the D of
+     * the cell's primitives; a ghost cell, a copy of its interior image,
+     * carries the image's value (as the given field does) */
+    const T* sg = sig;
+    std::vector<T> smod;
+    if (gr.sigma_model != 0) {
+        smod.assign((size_t)Np, T(0.0));
+#pragma omp parallel for schedule(static)
+        for (long o = 0; o < Np; ++o) {
+            T mf[NM], P[NF], U[NF];
+            load_metric(metric, Np, o, mf);
+            Metric<T> m;
+            metric_point(mf, m);
+            for (int a = 0; a < NF; ++a) P[a] = Pst[(long)a * Np + o];
+            T v[3] = {P[P_V], P[P_V + 1], P[P_V + 2]}, vl[3];
+            lower(m, v, vl);
+            if (!(val(P[P_RHO]) > 0.0) || !(val(dot3(vl, v)) < 1.0)) continue;   /* cells no face reads */
+            prim2con(m, G, P, U);
+            smod[(size_t)o] = conductivity(gr, T(0.0), U[U_D]);
+        }
+        ghost_fill(gr, ge, smod.data(), 1);
+        sg = smod.data();
+    }
     /* sources */
 #pragma omp parallel for collapse(2) schedule(static)
     for (int k = ge.g[2]; k < ge.g[2] + gr.n[2]; ++k)
@@ -1041,13 +1065,7 @@ void explicit_rhs(const Grid& gr, const Geo& ge, const T* metric, const T* Pst, 
                             load_metric(metric, Np, oc, mc);
                             Metric<T> mm;
                             metric_point(mc, mm);
-                            T sc = sig[oc];
-                            if (gr.sigma_model != 0) {
-                                T Uc[NF];
-                                prim2con(mm, G, Pc, Uc);
-                                sc = conductivity(gr, sc, Uc[U_D]);
-                            }
-                            cell_current(mm, G, Pc, sc, Jc[side]);
+                            cell_current(mm, G, Pc, sg[oc], Jc[side]);
                         }
                         Jf = 0.5 * (Jc[0][d] + Jc[1][d]);
                     }

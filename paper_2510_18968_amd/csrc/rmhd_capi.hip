@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -22,8 +23,9 @@ struct rmhd_ctx {
     char* ws;
     size_t ws_bytes;
     double *rhs, *P1, *R1, *U2, *P2, *R2;
+    double* sigf;                   // conductivity-model field of the stage primitives (models only)
     unsigned long long* counters;   // [0] failed recoveries, [1] max signal speed bits, [2] metric scan flag,
-                                    // [3] dummy status word;
+                                    // [3] dummy status word, [4] atmosphere cells;
                                     // [32..127] recovery iteration histograms
     bool curved;
     int device = 0;                 // the device current at rmhd_init_grid
@@ -106,6 +108,17 @@ bool check_desc(const rmhd_grid_desc* d, std::string& why) {
     if (!(d->c2p_tol > 0.0) || d->c2p_maxit < 1) { why = "bad recovery tolerance or cap"; return false; }
     if (d->speed_mode != 0 && d->speed_mode != 1) { why = "bad speed_mode"; return false; }
     if (d->x_align != 0 && d->x_align != 1) { why = "x_align must be 0 or 1"; return false; }
+    if (d->sigma_model < RMHD_SIGMA_FIELD || d->sigma_model > RMHD_SIGMA_DYNAMO) { why = "bad sigma_model"; return false; }
+    if (d->sigma_model != RMHD_SIGMA_FIELD &&
+        !(d->sigma0 >= 0.0 && d->sigma0 < 1e300 && d->sigma_exp > -1e300 && d->sigma_exp < 1e300 &&
+          d->sigma_Datmo >= 0.0 && d->sigma_Datmo < 1e300)) {
+        why = "conductivity model: sigma0 and sigma_Datmo must be >= 0 and finite, sigma_exp finite";
+        return false;
+    }
+    if (!(d->rho_atmo >= 0.0 && d->rho_atmo < 1e300) || !(d->K_atmo >= 0.0 && d->K_atmo < 1e300)) {
+        why = "rho_atmo and K_atmo must be >= 0 and finite";
+        return false;
+    }
     long np = 1;
     for (int k = 0; k < 3; ++k) np *= d->n[k] + 2 * pad_lo(d, k);
     if (np > (1L << 36)) { why = "grid too large"; return false; }
@@ -120,7 +133,7 @@ long padded_cells(const rmhd_grid_desc* d) {
     return np;
 }
 
-size_t ws_layout(const rmhd_grid_desc* d, size_t off[7]) {
+size_t ws_layout(const rmhd_grid_desc* d, size_t off[8]) {
     const size_t Np = (size_t)padded_cells(d);
     const size_t f14 = up(14 * Np * sizeof(double)), f3 = up(3 * Np * sizeof(double));
     size_t o = 0;
@@ -130,7 +143,8 @@ size_t ws_layout(const rmhd_grid_desc* d, size_t off[7]) {
     off[3] = o; o += f14;   // U2
     off[4] = o; o += f14;   // P2
     off[5] = o; o += f3;    // R2
-    off[6] = o; o += 4 * ALIGN; // counters: 32 words, then the 96 histogram bins
+    off[6] = o; o += d->sigma_model != RMHD_SIGMA_FIELD ? up(Np * sizeof(double)) : 0;   // model sigma field
+    off[7] = o; o += 4 * ALIGN; // counters: 32 words, then the 96 histogram bins
     return o;
 }
 
@@ -285,6 +299,9 @@ int launch_stage(rmhd_ctx* c, double dt, const double* sig, const double* Un, co
 
 int stage1(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* Pg, double* P1, double* R1,
            double* U1, int32_t* st) {
+    // with a conductivity model the kernel takes sigma from D^n; the sigma
+    // stream it loads is then a placeholder (the model's own buffer)
+    if (c->desc.sigma_model != RMHD_SIGMA_FIELD) sig = c->sigf;
     Timed t(c, T_STAGE1);
     return launch_stage<1>(c, dt, sig, Un, nullptr, Pg, nullptr, nullptr, U1, P1, R1, st);
 }
@@ -296,20 +313,43 @@ int update(rmhd_ctx* c, double dt, const double* sig, const double* Un, const do
     return launch_stage<STAGE>(c, dt, sig, Un, Us, Ps, R1, R2, Uo, Po, Ro, st);
 }
 
+// the sigma the flux sweeps read: the caller's field, or with a conductivity
+// model the model at the stage primitives P (interior cells; the sweeps take
+// ghost cells from their interior images)
+int flux_sigma(rmhd_ctx* c, const double* P, const double* sig, const double** out) {
+    if (c->desc.sigma_model == RMHD_SIGMA_FIELD) {
+        *out = sig;
+        return RMHD_OK;
+    }
+    const long n = ncells(c->p);
+    Timed t(c, T_OTHER);
+    if (c->curved) k_sigma_field<true><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, P, c->sigf);
+    else k_sigma_field<false><<<nblk(n, 256), 256, 0, c->stream>>>(c->p, P, c->sigf);
+    LAUNCH_CHECK();
+    *out = c->sigf;
+    return RMHD_OK;
+}
+
 int stage2(rmhd_ctx* c, double dt, const double* sig, const double* Un, double* P1, const double* R1, double* U2,
            double* P2, double* R2, int32_t* st) {
     int r;
     if ((r = ghost_fill(c, P1, NF)) != RMHD_OK) return r;
-    if ((r = flux_div(c, P1, sig)) != RMHD_OK) return r;
-    return update<2>(c, dt, sig, Un, nullptr, P1, R1, nullptr, U2, P2, R2, st);
+    const double* fs = nullptr;
+    if ((r = flux_sigma(c, P1, sig, &fs)) != RMHD_OK) return r;
+    if ((r = flux_div(c, P1, fs)) != RMHD_OK) return r;
+    // (with a model the stage kernel takes sigma from D of its stage state;
+    // the sigma stream it loads is then a placeholder)
+    return update<2>(c, dt, fs, Un, nullptr, P1, R1, nullptr, U2, P2, R2, st);
 }
 
 int stage3(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* U2, double* P2,
            const double* R1, const double* R2, double* Uo, double* Po, int32_t* st) {
     int r;
     if ((r = ghost_fill(c, P2, NF)) != RMHD_OK) return r;
-    if ((r = flux_div(c, P2, sig)) != RMHD_OK) return r;
-    return update<3>(c, dt, sig, Un, U2, P2, R1, R2, Uo, Po, nullptr, st);
+    const double* fs = nullptr;
+    if ((r = flux_sigma(c, P2, sig, &fs)) != RMHD_OK) return r;
+    if ((r = flux_div(c, P2, fs)) != RMHD_OK) return r;
+    return update<3>(c, dt, fs, Un, U2, P2, R1, R2, Uo, Po, nullptr, st);
 }
 
 constexpr int ADJ_FIELDS = 79;   // Ub2 14, Pb 14, Lb 14, R1b 3, R2b 3, sb 1, fb 30
@@ -426,6 +466,8 @@ int rmhd_step_adjoint(rmhd_ctx* c, double dt, const double* sigma, const double*
         return fail(RMHD_EINVAL, "null argument");
     if (!(dt > 0.0)) return fail(RMHD_EINVAL, "dt must be > 0");
     if (c->desc.precision != RMHD_PREC_FP64) return fail(RMHD_EINVAL, "the adjoint differentiates the FP64 form");
+    if (c->desc.sigma_model != RMHD_SIGMA_FIELD || c->desc.rho_atmo > 0.0)
+        return fail(RMHD_EINVAL, "the adjoint differentiates the static sigma field without an atmosphere");
     if (adj_bytes < rmhd_adjoint_workspace_bytes(&c->desc)) return fail(RMHD_EINVAL, "adjoint workspace too small");
     if ((reinterpret_cast<uintptr_t>(adj_ws) % ALIGN) != 0) return fail(RMHD_EINVAL, "adjoint workspace not aligned");
     const long Np = c->p.Np;
@@ -496,7 +538,7 @@ size_t rmhd_workspace_bytes(const rmhd_grid_desc* desc) {
         g_err = why;
         return 0;
     }
-    size_t off[7];
+    size_t off[8];
     return ws_layout(desc, off);
 }
 
@@ -513,7 +555,7 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     if (!out) return fail(RMHD_EINVAL, "out is null");
     *out = nullptr;
     if (!check_desc(desc, why)) return fail(RMHD_EINVAL, why);
-    size_t off[7];
+    size_t off[8];
     const size_t need = ws_layout(desc, off);
     if (!workspace || ws_bytes < need)
         return fail(RMHD_EINVAL, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -529,7 +571,8 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     c->U2 = reinterpret_cast<double*>(c->ws + off[3]);
     c->P2 = reinterpret_cast<double*>(c->ws + off[4]);
     c->R2 = reinterpret_cast<double*>(c->ws + off[5]);
-    c->counters = reinterpret_cast<unsigned long long*>(c->ws + off[6]);
+    c->sigf = desc->sigma_model != RMHD_SIGMA_FIELD ? reinterpret_cast<double*>(c->ws + off[6]) : nullptr;
+    c->counters = reinterpret_cast<unsigned long long*>(c->ws + off[7]);
     Params& p = c->p;
     std::memset(&p, 0, sizeof p);
     for (int d = 0; d < 3; ++d) {
@@ -551,6 +594,12 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     p.G = desc->gamma_ad;
     p.kappa = desc->kappa;
     p.tol = desc->c2p_tol;
+    p.sig_model = desc->sigma_model;
+    p.sig0 = desc->sigma0;
+    p.sig_exp = desc->sigma_exp;
+    p.sig_Datmo = desc->sigma_Datmo;
+    p.rho_atmo = desc->rho_atmo;
+    p.p_atmo = desc->rho_atmo > 0.0 ? desc->K_atmo * std::pow(desc->rho_atmo, desc->gamma_ad) : 0.0;
     c->curved = false;
     {
         int dev = 0, cus = 0;
@@ -565,7 +614,7 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
             c->scratch_err = "hipGetDevice failed at rmhd_init_grid";
         }
     }
-    k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 2);
+    k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 5);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         delete c;
@@ -622,7 +671,7 @@ int rmhd_con2prim(rmhd_ctx* c, const double* U, double* P, int32_t* status) {
 }
 
 int rmhd_imex_stage(rmhd_ctx* c, int stage, double dt, const double* sigma, const rmhd_stage_bufs* b) {
-    if (!c || !b || !sigma) return fail(RMHD_EINVAL, "null argument");
+    if (!c || !b || (!sigma && c->desc.sigma_model == RMHD_SIGMA_FIELD)) return fail(RMHD_EINVAL, "null argument");
     if (!(dt > 0.0)) return fail(RMHD_EINVAL, "dt must be > 0");
     if (!b->U_n || !b->P_in || !b->P_out) return fail(RMHD_EINVAL, "U_n, P_in and P_out are required");
     switch (stage) {
@@ -645,7 +694,8 @@ int rmhd_imex_stage(rmhd_ctx* c, int stage, double dt, const double* sigma, cons
 }
 
 int rmhd_step(rmhd_ctx* c, double dt, const double* sigma, double* U, double* P) {
-    if (!c || !sigma || !U || !P) return fail(RMHD_EINVAL, "null argument");
+    if (!c || !U || !P || (!sigma && c->desc.sigma_model == RMHD_SIGMA_FIELD))
+        return fail(RMHD_EINVAL, "null argument");
     if (!(dt > 0.0)) return fail(RMHD_EINVAL, "dt must be > 0");
     int r;
     if ((r = stage1(c, dt, sigma, U, P, c->P1, c->R1, nullptr, nullptr)) != RMHD_OK) return r;
@@ -677,6 +727,17 @@ int rmhd_failures(rmhd_ctx* c, int64_t* host_out) {
     HIP_TRY(hipMemcpyAsync(&n, c->counters, sizeof n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
     k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters, 1);
+    LAUNCH_CHECK();
+    *host_out = (int64_t)n;
+    return RMHD_OK;
+}
+
+int rmhd_atmosphere_cells(rmhd_ctx* c, int64_t* host_out) {
+    if (!c || !host_out) return fail(RMHD_EINVAL, "null argument");
+    unsigned long long n = 0;
+    HIP_TRY(hipMemcpyAsync(&n, c->counters + 4, sizeof n, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    k_zero_u64<<<1, 64, 0, c->stream>>>(c->counters + 4, 1);
     LAUNCH_CHECK();
     *host_out = (int64_t)n;
     return RMHD_OK;

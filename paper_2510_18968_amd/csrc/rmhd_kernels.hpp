@@ -31,7 +31,21 @@ struct Params {
     const double* K;
     // opt-in histograms of recovery iterations (3 x RMHD_HIST_BINS), nullptr = off
     unsigned long long* hist;
+    // conductivity model (0: the sigma field) and the artificial atmosphere
+    // (rho_atmo = 0: off; p_atmo = K_atmo rho_atmo^Gamma)
+    int sig_model;
+    double sig0, sig_exp, sig_Datmo, rho_atmo, p_atmo;
 };
+
+// conductivity from the conserved rest-mass density D (Sec. IV.A eq.
+// sigma_evol: sigma0 D^gamma; Sec. IV.E eq. dynamo_sigma: sigma0 max(1 -
+// D_atmo/D, 0)^2); only called when a model is selected
+__device__ __forceinline__ double sigma_of_D(const Params& p, double D) {
+    if (p.sig_model == 1) return p.sig0 * pow(D, p.sig_exp);
+    const double t = fmax(1.0 - p.sig_Datmo / D, 0.0);
+    return p.sig0 * t * t;
+}
+constexpr double ATMO_FACTOR = 1.01;
 
 __host__ __device__ __forceinline__ bool is_active(const Params& p, int d) { return (p.active >> d) & 1; }
 
@@ -953,7 +967,7 @@ __host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560;
 // chunk's loads and the wait for them
 struct StageTally {
     unsigned int hist[32];
-    unsigned int fail;
+    unsigned int fail, atmo;
 };
 __device__ __forceinline__ void tally_cell(StageTally& t, bool hist, bool counted, int st, int it) {
     if (!counted) return;
@@ -1133,7 +1147,7 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
         for (int f = 0; f < NF; ++f)
             if (f < I_E || f >= I_E + 3) U1[f * Np + o] = in.Un[f];
     const double gdt = GAM_IMEX() * dt;
-    k.cfac = gdt * m.alp * in.sg;
+    k.cfac = gdt * m.alp * (p.sig_model ? sigma_of_D(p, in.Un[I_D]) : in.sg);
     double x[4] = {in.P[I_P], in.P[I_V], in.P[I_V + 1], in.P[I_V + 2]};
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
@@ -1166,6 +1180,8 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     RecIn k;
     double x[4] = {in.P[I_P], in.P[I_V], in.P[I_V + 1], in.P[I_V + 2]};
     double cl[3];
+    double YD;
+    bool atmo = false;
     {
         double Y[NF];
         {
@@ -1185,6 +1201,19 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
                 for (int i = 0; i < 3; ++i) Y[I_E + i] += 0.5 * dt * (2.0 * g * in.R1[i] + (1.0 - g) * in.R2[i]);
             }
         }
+        if (STAGE == 3 && p.rho_atmo > 0.0 && Y[I_D] < ATMO_FACTOR * m.sg * p.rho_atmo) {
+            // artificial atmosphere (Sec. IV.E): the hydro part of the state
+            // rho_atmo, v = 0, p_atmo with the cell's own fields
+            double Pa[NF], Ua[NF];
+            Pa[I_RHO] = p.rho_atmo;
+            Pa[I_P] = p.p_atmo;
+            for (int i = 0; i < 3; ++i) Pa[I_V + i] = 0.0;
+            for (int f = I_B; f < NF; ++f) Pa[f] = Y[f] * m.isg;
+            prim2con(m, p.G, Pa, Ua);
+            for (int f = I_D; f <= I_TAU; ++f) Y[f] = Ua[f];
+            atmo = true;
+        }
+        YD = Y[I_D];
         __builtin_amdgcn_sched_barrier(0);
         for (int f = 0; f < NF; ++f)
             if (STAGE == 3 || f < I_E || f >= I_E + 3) Uo[f * Np + o] = Y[f];
@@ -1199,7 +1228,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
     if (STAGE == 2) {
-        k.cfac = g * dt * m.alp * in.sg;
+        k.cfac = g * dt * m.alp * (p.sig_model ? sigma_of_D(p, YD) : in.sg);
         if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
         else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     } else {
@@ -1207,6 +1236,11 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     }
     __builtin_amdgcn_sched_barrier(0);
     tally_cell(tal, p.hist != nullptr, in.ok, st, it);
+    (void)YD;
+    if (STAGE == 3 && atmo && st >= 0) {
+        st = 2;                                           // flagged: atmosphere
+        if (in.ok) atomicAdd(&tal.atmo, 1u);
+    }
     if (st < 0) {
         // failed (flagged): the primitives of the stage state at the guess's
         // p and v with E = E*; every store below is taken on every path
@@ -1249,7 +1283,7 @@ __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const d
     __shared__ StageTally tal;
     const int lane = threadIdx.x;
     if (lane < 32) tal.hist[lane] = 0u;
-    if (lane == 0) tal.fail = 0u;
+    if (lane == 0) tal.fail = tal.atmo = 0u;
     const int nsx = (p.n[0] + 63) / 64;
     const long nchunk = (long)nsx * p.n[1] * p.n[2];
     const long W = gridDim.x;
@@ -1283,6 +1317,24 @@ __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const d
     if (p.hist && lane < 32 && tal.hist[lane])
         atomicAdd(p.hist + 32 * (STAGE - 1) + lane, (unsigned long long)tal.hist[lane]);
     if (lane == 0 && tal.fail) atomicAdd(nfail, (unsigned long long)tal.fail);
+    // nfail[4]: cells set to the atmosphere (the context's counter block)
+    if (STAGE == 3 && lane == 0 && tal.atmo) atomicAdd(nfail + 4, (unsigned long long)tal.atmo);
+}
+
+// conductivity model at the interior cells from the primitives P (D =
+// sqrt(gamma) rho W), for the charge flux of the stage operator
+template <bool CURVED>
+__global__ __launch_bounds__(256) void k_sigma_field(const Params p, const double* __restrict__ P,
+                                                     double* __restrict__ out) {
+    long o;
+    if (!interior_cell(p, (long)blockIdx.x * blockDim.x + threadIdx.x, o)) return;
+    Geo<double> m;
+    cell_geo<CURVED>(p, o, m);
+    const double v[3] = {P[I_V * p.Np + o], P[(I_V + 1) * p.Np + o], P[(I_V + 2) * p.Np + o]};
+    double vl[3];
+    lower(m.g, v, vl);
+    const double W = frsqrt(1.0 - dot3(vl, v));
+    out[o] = sigma_of_D(p, P[I_RHO * p.Np + o] * W * m.sg);
 }
 
 // ---------------------------------------------------- max signal speed (CFL)

@@ -18,12 +18,13 @@ LIB_PATH = os.path.join(_HERE, "librmhd.so")
 RECON = {"minmod": 0, "mc2": 1, "weno5": 2}
 BC = {"periodic": 0, "copy": 1}
 PREC = {"fp64": 0, "mixed": 1}
+SIGMA_MODEL = {"field": 0, "power": 1, "dynamo": 2}
 
 SYMBOLS = ("rmhd_workspace_bytes", "rmhd_padded_extent", "rmhd_init_grid", "rmhd_set_metric", "rmhd_prim2con", "rmhd_con2prim",
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
            "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
            "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read", "rmhd_set_stream",
-           "rmhd_step_adjoint_static")
+           "rmhd_step_adjoint_static", "rmhd_atmosphere_cells")
 HIST_BINS = 32
 TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
 
@@ -32,7 +33,10 @@ class GridDesc(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("active_mask", C.c_int32), ("ng", C.c_int32), ("bc", C.c_int32 * 3),
                 ("recon", C.c_int32), ("precision", C.c_int32), ("c2p_maxit", C.c_int32),
                 ("speed_mode", C.c_int32), ("x_align", C.c_int32), ("x0", C.c_double * 3), ("dx", C.c_double * 3),
-                ("gamma_ad", C.c_double), ("kappa", C.c_double), ("c2p_tol", C.c_double)]
+                ("gamma_ad", C.c_double), ("kappa", C.c_double), ("c2p_tol", C.c_double),
+                ("sigma_model", C.c_int32), ("reserved_", C.c_int32), ("sigma0", C.c_double),
+                ("sigma_exp", C.c_double), ("sigma_Datmo", C.c_double), ("rho_atmo", C.c_double),
+                ("K_atmo", C.c_double)]
 
 
 class StageBufs(C.Structure):
@@ -68,6 +72,7 @@ def lib() -> C.CDLL:
             "rmhd_step": (C.c_int, [vp, C.c_double, vp, vp, vp]),
             "rmhd_max_signal_speed": (C.c_int, [vp, C.POINTER(C.c_double)]),
             "rmhd_failures": (C.c_int, [vp, C.POINTER(C.c_int64)]),
+            "rmhd_atmosphere_cells": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "rmhd_destroy": (C.c_int, [vp]),
             "rmhd_last_error": (C.c_char_p, []),
             "rmhd_timing": (C.c_int, [vp, C.c_int]),
@@ -93,7 +98,8 @@ def _check(rc: int, what: str):
 
 
 def make_desc(n, active, dx, bc, gamma_ad, recon="weno5", x0=(0.0, 0.0, 0.0), kappa=1.0, precision="fp64",
-              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0, x_align=0) -> GridDesc:
+              c2p_tol=1e-14, c2p_maxit=500, speed_mode=0, x_align=0, sigma_model=0, sigma0=0.0, sigma_exp=0.0,
+              sigma_Datmo=0.0, rho_atmo=0.0, K_atmo=0.0) -> GridDesc:
     d = GridDesc()
     for k in range(3):
         d.n[k] = int(n[k])
@@ -105,6 +111,10 @@ def make_desc(n, active, dx, bc, gamma_ad, recon="weno5", x0=(0.0, 0.0, 0.0), ka
     d.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     d.c2p_maxit, d.speed_mode, d.x_align = int(c2p_maxit), int(speed_mode), int(x_align)
     d.gamma_ad, d.kappa, d.c2p_tol = float(gamma_ad), float(kappa), float(c2p_tol)
+    d.sigma_model = SIGMA_MODEL[sigma_model] if isinstance(sigma_model, str) else int(sigma_model)
+    d.reserved_ = 0
+    d.sigma0, d.sigma_exp, d.sigma_Datmo = float(sigma0), float(sigma_exp), float(sigma_Datmo)
+    d.rho_atmo, d.K_atmo = float(rho_atmo), float(K_atmo)
     return d
 
 
@@ -254,6 +264,12 @@ class Grid:
         _check(lib().rmhd_failures(self._ctx, C.byref(v)), "rmhd_failures")
         return int(v.value)
 
+    def atmosphere_cells(self) -> int:
+        """cells set to the atmosphere state since the last call"""
+        v = C.c_int64()
+        _check(lib().rmhd_atmosphere_cells(self._ctx, C.byref(v)), "rmhd_atmosphere_cells")
+        return int(v.value)
+
     def step_adjoint(self, dt, sigma, U_n, P_n, Ubar_np1, Ubar_n, sigma_bar):
         """Ubar_n = (dU^{n+1}/dU^n)^T Ubar_np1; sigma_bar += (dU^{n+1}/dsigma)^T Ubar_np1.
         Ubar_n may be Ubar_np1 (in place)."""
@@ -317,6 +333,9 @@ class Grid:
 def grid_for(w, device="cuda", **kw) -> Grid:
     """A Grid for a workload of ``paper_2510_18968_amd.workloads``."""
     recon = {0: "minmod", 1: "mc2", 2: "weno5"}[w.recon]
-    d = make_desc(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=kw.pop("recon", recon), x0=w.x0, kappa=w.kappa,
-                  **kw)
+    # the workload's conductivity model and atmosphere, if it names them
+    model = dict(w.extra.get("model", {}))
+    model.update(kw)
+    d = make_desc(w.n, w.active, w.dx, w.bc, w.gamma_ad, recon=model.pop("recon", recon), x0=w.x0, kappa=w.kappa,
+                  **model)
     return Grid(d, device)

@@ -205,7 +205,7 @@ def periodic_box(n=128, seed=201, cfl=0.4, steps=10) -> Workload:
 
 
 # ----------------------------------------------------------------- config 3
-def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20, shift=0.0) -> Workload:
+def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20, shift=0.0, atmosphere=False) -> Workload:
     """Static conformally flat background on [-1,1]^3 (gamma_ij = psi^4
     delta_ij, psi = 1 + 0.1 exp(-r^2/0.25), alpha = 1 - 0.3 exp(-r^2/0.25),
     zero shift and extrinsic curvature), a seeded density blob
@@ -215,7 +215,11 @@ def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20, shift=0.0) -
     shift != 0 adds a smooth shift beta = shift b(r) (y, -x, z/2) and
     extrinsic curvature K_ij = shift b(r) k_ij (fixed symmetric k), b the bump,
     to exercise every metric term (input fields, not a solution of Einstein's
-    equations)."""
+    equations).  atmosphere=True selects the stellar-exterior treatment of
+    Sec. IV.E instead of the static sigma: sigma = 1e6 max(1 - D_atmo/D, 0)^2
+    (eq. dynamo_sigma) with D_atmo = 1e-3, and the artificial atmosphere at
+    rho_atmo = 1e-3 with the paper's polytrope K = 100 (Gamma = 2, which is
+    also the blob's p = 100 rho^2)."""
     rng = np.random.default_rng(seed)
     dx = 2.0 / n
     nn = (n, n, n)
@@ -263,8 +267,12 @@ def curved_blob(n=256, seed=301, recon="weno5", cfl=0.25, steps=20, shift=0.0) -
     P[5], P[6], P[7] = Bx * scale, By * scale, Bz * scale
     rho_max = float(P[0][inner].max())
     sigma = 1e6 * P[0] / rho_max + 1.0
-    return Workload(f"curved_blob_{n}^3_{recon}" + ("_shift" if shift else ""), nn, 7, (dx,) * 3, (x0,) * 3, (1, 1, 1), 2.0, RECON[recon],
-                    cfl * dx, steps, P, sigma, met, extra=dict(seed=seed, cfl=cfl))
+    extra = dict(seed=seed, cfl=cfl)
+    if atmosphere:
+        extra["model"] = dict(sigma_model=2, sigma0=1e6, sigma_Datmo=1e-3, rho_atmo=1e-3, K_atmo=100.0)
+    name = f"curved_blob_{n}^3_{recon}" + ("_shift" if shift else "") + ("_atmo" if atmosphere else "")
+    return Workload(name, nn, 7, (dx,) * 3, (x0,) * 3, (1, 1, 1), 2.0, RECON[recon],
+                    cfl * dx, steps, P, sigma, met, extra=extra)
 
 
 # ----------------------------------------------------------------- config 5
@@ -304,9 +312,9 @@ def sheet_batch(nprob=64, n=2048, seed=501, target_seed=502, cfl=0.25, steps=200
 def brio_wu(sigma0=1e6, n=400, cfl=0.25, t_end=0.4, sigma_exp=None) -> Workload:
     """The shocktube of Sec. IV.A as printed: (rho, p, B^y) = (1, 1, 0.5) for
     x < 0 and (0.125, 0.1, -0.5) for x > 0, v = B^x = B^z = E = 0, Gamma = 2,
-    minmod, copy boundaries, on [-0.5, 0.5] with Delta x = 1/n.  sigma_exp
-    (gamma of eq. sigma_evol) is recorded for the sigma(D) model; the static
-    sigma field is sigma0."""
+    minmod, copy boundaries, on [-0.5, 0.5] with Delta x = 1/n.  With
+    sigma_exp (gamma of eq. sigma_evol) the conductivity is the model sigma0
+    D^gamma; otherwise the static field sigma0."""
     dx = 1.0 / n
     nn = (n, 1, 1)
     x0 = -0.5 + 0.5 * dx
@@ -319,8 +327,11 @@ def brio_wu(sigma0=1e6, n=400, cfl=0.25, t_end=0.4, sigma_exp=None) -> Workload:
     P[6] = np.where(left, 0.5, -0.5)
     sigma = np.full(shape, float(sigma0))
     steps = int(round(t_end / (cfl * dx)))
-    return Workload(f"brio_wu_{n}", nn, 1, (dx, 1.0, 1.0), (x0, 0.0, 0.0), (1, 1, 1), 2.0, RECON["minmod"],
-                    t_end / steps, steps, P, sigma, None, extra=dict(sigma0=sigma0, sigma_exp=sigma_exp, cfl=cfl))
+    extra = dict(sigma0=sigma0, sigma_exp=sigma_exp, cfl=cfl)
+    if sigma_exp is not None:
+        extra["model"] = dict(sigma_model=1, sigma0=sigma0, sigma_exp=float(sigma_exp))
+    return Workload(f"brio_wu_{n}" + ("" if sigma_exp is None else f"_gamma{sigma_exp:g}"), nn, 1, (dx, 1.0, 1.0),
+                    (x0, 0.0, 0.0), (1, 1, 1), 2.0, RECON["minmod"], t_end / steps, steps, P, sigma, None, extra=extra)
 
 
 def alfven_speed(rho, p, eta_A, B0, gamma_ad):
