@@ -37,6 +37,18 @@ def build(force: bool = True) -> str:
     return _LIB
 
 
+def build_sanitized(out_dir: str) -> str:
+    """Compile oracle/sanitize_main.cpp (the oracle's source plus a driver
+    that calls every grid entry point on small grids) with the address and
+    undefined-behaviour sanitizers, into out_dir; returns the executable."""
+    exe = os.path.join(out_dir, "oracle_sanitized")
+    src = os.path.join(os.path.dirname(_SRC), "sanitize_main.cpp")
+    cmd = ["g++", "-O1", "-g", "-ffp-contract=off", "-fopenmp", "-std=c++17", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-I", os.path.dirname(_SRC), "-o", exe, src]
+    subprocess.run(cmd, check=True)
+    return exe
+
+
 class Grid(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("active", C.c_int32), ("ng", C.c_int32), ("bc", C.c_int32 * 3),
                 ("recon", C.c_int32), ("c2p_maxit", C.c_int32), ("speed_mode", C.c_int32),
