@@ -28,6 +28,7 @@ struct rmhd_ctx {
                                     // [3] dummy status word, [4] atmosphere cells;
                                     // [32..127] recovery iteration histograms
     bool curved;
+    bool diag = false;              // curved with gamma_xy = gamma_xz = gamma_yz = 0 everywhere
     int device = 0;                 // the device current at rmhd_init_grid
     void* scratch = nullptr;        // that device's copy of the static adjoint scratch (or null)
     std::string scratch_err;        // why it could not be resolved
@@ -197,7 +198,7 @@ int ghost_fill(rmhd_ctx* c, double* a, int nf) {
 // x fluxes: in FP64 the persistent kernel (one wave per SIMD walking the
 // segments with the next segment's loads in flight) is faster; in FP32 the
 // one-segment-per-wave kernel is (measured on the 256^3 curved workload)
-template <int D, int RECON, bool CURVED, class R, bool ACC> void flux_t(rmhd_ctx* c, const double* P,
+template <int D, int RECON, bool CURVED, class R, bool ACC, bool DG> void flux_t(rmhd_ctx* c, const double* P,
                                                                      const double* sig) {
     const Params& p = c->p;
     constexpr int E1 = (D == 0) ? 1 : 0, E2 = (D == 2) ? 1 : 2;
@@ -207,14 +208,14 @@ template <int D, int RECON, bool CURVED, class R, bool ACC> void flux_t(rmhd_ctx
     const long items = ((long)(p.n[0] + 6) * p.n[E1] * p.n[E2] + TSEG - 1) / TSEG;
     const long need = (nblk(items, 4) + 7) / 8 * 8;   // multiple of 8 for the XCD renumbering
     if constexpr (std::is_same<R, float>::value) {
-        k_flux_t<D, RECON, CURVED, R, ACC><<<need, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);
+        k_flux_t<D, RECON, CURVED, R, ACC, DG><<<need, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);
     } else {
         const long blocks = std::min<long>(need, c->persist_blocks);
-        k_flux_p<D, RECON, CURVED, R, ACC><<<blocks, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);
+        k_flux_p<D, RECON, CURVED, R, ACC, DG><<<blocks, 256, 0, c->stream>>>(p, P, sig, c->rhs, nseg, items);
     }
 }
 
-template <int D, int RECON, bool CURVED, class R> void flux_w(rmhd_ctx* c, const double* P, const double* sig) {
+template <int D, int RECON, bool CURVED, class R, bool DG> void flux_w(rmhd_ctx* c, const double* P, const double* sig) {
     const Params& p = c->p;
     constexpr int E = (D == 1) ? 2 : 1;
     // segments as long as possible (each re-loads 3 halo rows at both ends
@@ -229,26 +230,26 @@ template <int D, int RECON, bool CURVED, class R> void flux_w(rmhd_ctx* c, const
     const long waves = (long)nxb * p.n[E] * nseg;
     const long blocks = (waves + 7) / 8 * 8;          // one wave per block; multiple of 8 for the XCD renumbering
     if (CURVED && p.bet)
-        k_flux_w<D, RECON, CURVED, R, true><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+        k_flux_w<D, RECON, CURVED, R, true, DG><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
     else
-        k_flux_w<D, RECON, CURVED, R, false><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+        k_flux_w<D, RECON, CURVED, R, false, DG><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
 }
 
-template <int RECON, bool CURVED, class R> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
+template <int RECON, bool CURVED, class R, bool DG> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
     const Params& p = c->p;
     {
         Timed t(c, T_FX);
-        flux_t<0, RECON, CURVED, R, false>(c, P, sig);
+        flux_t<0, RECON, CURVED, R, false, DG>(c, P, sig);
     }
     LAUNCH_CHECK();
     if (is_active(p, 1)) {
         Timed t(c, T_FY);
-        flux_w<1, RECON, CURVED, R>(c, P, sig);
+        flux_w<1, RECON, CURVED, R, DG>(c, P, sig);
         LAUNCH_CHECK();
     }
     if (is_active(p, 2)) {
         Timed t(c, T_FZ);
-        flux_w<2, RECON, CURVED, R>(c, P, sig);
+        flux_w<2, RECON, CURVED, R, DG>(c, P, sig);
         LAUNCH_CHECK();
     }
     return RMHD_OK;
@@ -256,14 +257,19 @@ template <int RECON, bool CURVED, class R> int flux_div_t(rmhd_ctx* c, const dou
 
 template <class R> int flux_div_r(rmhd_ctx* c, const double* P, const double* sig) {
     const int r = c->desc.recon;
-    if (c->curved) {
-        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R>(c, P, sig);
-        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R>(c, P, sig);
-        return flux_div_t<REC_WENO5, true, R>(c, P, sig);
+    if (c->curved && c->diag) {
+        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R, true>(c, P, sig);
+        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R, true>(c, P, sig);
+        return flux_div_t<REC_WENO5, true, R, true>(c, P, sig);
     }
-    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false, R>(c, P, sig);
-    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false, R>(c, P, sig);
-    return flux_div_t<REC_WENO5, false, R>(c, P, sig);
+    if (c->curved) {
+        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R, false>(c, P, sig);
+        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R, false>(c, P, sig);
+        return flux_div_t<REC_WENO5, true, R, false>(c, P, sig);
+    }
+    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false, R, false>(c, P, sig);
+    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false, R, false>(c, P, sig);
+    return flux_div_t<REC_WENO5, false, R, false>(c, P, sig);
 }
 
 // minus the flux divergence of the (ghost-filled) primitives P into c->rhs;
@@ -284,15 +290,18 @@ int launch_stage(rmhd_ctx* c, double dt, const double* sig, const double* Un, co
     // without a status array every cell writes one dummy word (counters[3])
     int32_t* sp = st ? st : reinterpret_cast<int32_t*>(c->counters + 3);
     const long ss = st ? 1 : 0;
-    if (c->curved && c->p.K)
-        k_stage<STAGE, true, true><<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                   Ro, sp, ss, c->counters);
-    else if (c->curved)
-        k_stage<STAGE, true, false><<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                    Ro, sp, ss, c->counters);
-    else
-        k_stage<STAGE, false, false><<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po,
-                                                                     Ro, sp, ss, c->counters);
+    auto go = [&](auto kern) {
+        kern<<<blocks, 64, 0, c->stream>>>(c->p, dt, sig, Un, Us, Ps, R1, R2, c->rhs, Uo, Po, Ro, sp, ss, c->counters);
+    };
+    if (c->curved && c->p.K) {
+        if (c->diag) go(k_stage<STAGE, true, true, true>);
+        else go(k_stage<STAGE, true, true, false>);
+    } else if (c->curved) {
+        if (c->diag) go(k_stage<STAGE, true, false, true>);
+        else go(k_stage<STAGE, true, false, false>);
+    } else {
+        go(k_stage<STAGE, false, false, false>);
+    }
     LAUNCH_CHECK();
     return RMHD_OK;
 }
@@ -640,10 +649,15 @@ int rmhd_set_metric(rmhd_ctx* c, const double* alpha, const double* beta, const 
         zero = h == 0;
         return RMHD_OK;
     };
-    bool zb = false, zk = false;
+    bool zb = false, zk = false, zxy = false, zyz = false;
     int r;
     if (beta && (r = all_zero(beta, 3 * c->p.Np, zb)) != RMHD_OK) return r;
     if (K && (r = all_zero(K, 6 * c->p.Np, zk)) != RMHD_OK) return r;
+    // a diagonal gamma_ij (xy, xz: rows 1-2; yz: row 4) selects the kernels
+    // that skip its zero entries
+    if (gamma && (r = all_zero(gamma + c->p.Np, 2 * c->p.Np, zxy)) != RMHD_OK) return r;
+    if (gamma && zxy && (r = all_zero(gamma + 4 * c->p.Np, c->p.Np, zyz)) != RMHD_OK) return r;
+    c->diag = gamma && zxy && zyz;
     c->p.alp = alpha;
     c->p.gam = gamma;
     c->p.bet = (beta && !zb) ? beta : nullptr;

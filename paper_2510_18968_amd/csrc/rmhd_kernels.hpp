@@ -75,7 +75,7 @@ template <class R> __device__ __forceinline__ void face_geo(const Params& p, lon
     geo_finish(m);
 }
 
-template <int D, class R> __device__ __forceinline__ void speeds(const Params& p, const Geo<R>& m, R& lp, R& lm) {
+template <int D, class R, bool DG> __device__ __forceinline__ void speeds(const Params& p, const Geo<R, DG>& m, R& lp, R& lm) {
     const R gdd = m.gi[sidx(D, D)];
     const R s = gdd * frsqrt(gdd);
     if (p.speed_mode == 0) {
@@ -91,16 +91,16 @@ template <int D, class R> __device__ __forceinline__ void speeds(const Params& p
 }
 
 // a face state is unusable if rho <= 0, p <= 0 or v^2 >= 1
-template <class R> __device__ __forceinline__ bool bad_state(const Geo<R>& m, const R* P) {
+template <class R, bool DG> __device__ __forceinline__ bool bad_state(const Geo<R, DG>& m, const R* P) {
     R vl[3];
-    lower(m.g, P + I_V, vl);
+    lower(m, P + I_V, vl);
     const R v2 = dot3(vl, P + I_V);
     return !(P[I_RHO] > R(0)) || !(P[I_P] > R(0)) || !(v2 < R(1));
 }
 
 // HLLE flux of direction D at a face with metric m (Sec. III)
-template <int D, class R>
-__device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, const R* PL, const R* PR, R Jd, R* Fh) {
+template <int D, class R, bool DG>
+__device__ __forceinline__ void face_flux(const Params& p, const Geo<R, DG>& m, const R* PL, const R* PR, R Jd, R* Fh) {
     R lp, lm;
     speeds<D>(p, m, lp, lm);
     const R id = frcp(lp - lm);
@@ -117,8 +117,8 @@ __device__ __forceinline__ void face_flux(const Params& p, const Geo<R>& m, cons
 }
 
 // the metric-derivative sources of one direction (defined with the stage kernels)
-template <int d, class R>
-__device__ __forceinline__ void sources_dir(const Params& p, const Geo<double>& m, double da, const double* db,
+template <int d, class R, bool DG>
+__device__ __forceinline__ void sources_dir(const Params& p, const Geo<double, DG>& m, double da, const double* db,
                                             const double* dg, const R* Pc, const R* Uc, R* S);
 
 // ----------------------------------------------------- fluxes, lanes along D
@@ -243,7 +243,7 @@ __device__ __forceinline__ FluxItem<D> flux_item(const Params& p, long wid, int 
     return it;
 }
 
-template <int D, bool CURVED>
+template <int D, bool CURVED, bool DG>
 __device__ __forceinline__ void flux_load(const Params& p, const double* __restrict__ P,
                                           const double* __restrict__ sig, const FluxItem<D>& it, FluxIn& in) {
     const long Np = p.Np, o = it.o;
@@ -251,7 +251,8 @@ __device__ __forceinline__ void flux_load(const Params& p, const double* __restr
     for (int f = 0; f < NF; ++f) in.P[f] = P[f * Np + o];
     if (CURVED) {
 #pragma unroll
-        for (int a = 0; a < 6; ++a) in.g[a] = p.gam[a * Np + o];
+        for (int a = 0; a < 6; ++a)
+            in.g[a] = zero_entry<DG>(a) ? 0.0 : p.gam[a * Np + o];
         in.a = p.alp[o];
         if (p.bet) {
 #pragma unroll
@@ -262,7 +263,7 @@ __device__ __forceinline__ void flux_load(const Params& p, const double* __restr
 }
 
 // minus the D-flux divergence of one segment into rhs (= or +=)
-template <int D, int RECON, bool CURVED, class R, bool ACC>
+template <int D, int RECON, bool CURVED, class R, bool ACC, bool DG>
 __device__ __forceinline__ void flux_compute(const Params& p, const double* __restrict__ P,
                                              double* __restrict__ rhs, const FluxItem<D>& it, const FluxIn& in,
                                              int lane) {
@@ -278,11 +279,12 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f] = 0.0;
     }
-    Geo<double> mc;   // the lane's cell
+    Geo<double, DG> mc;   // the lane's cell
     if (CURVED) {
         mc.alp = in.a;
         for (int a = 0; a < 3; ++a) mc.bet[a] = p.bet ? in.b[a] : 0.0;
-        for (int a = 0; a < 6; ++a) mc.g[a] = in.g[a];
+        for (int a = 0; a < 6; ++a)
+            if (!zero_entry<DG>(a)) mc.g[a] = in.g[a];
         geo_finish(mc);
     } else {
         geo_flat(mc);
@@ -307,12 +309,17 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
         recon<RECON>(st, fm[f], fp[f]);
     }
     // face between this lane's cell and the next
-    Geo<R> m;
+    Geo<R, DG> m;
     if (CURVED) {
         m.alp = R(face4(in.a));
         for (int a = 0; a < 3; ++a) m.bet[a] = p.bet ? R(face4(in.b[a])) : R(0);
         m.g[0] = R(face4(in.g[0]));
-        for (int a = 1; a < 6; ++a) m.g[a] = R(face4(after(in.g[a], m.g[a - 1])));
+        if (DG) {
+            m.g[3] = R(face4(after(in.g[3], m.g[0])));
+            m.g[5] = R(face4(after(in.g[5], m.g[3])));
+        } else {
+            for (int a = 1; a < 6; ++a) m.g[a] = R(face4(after(in.g[a], m.g[a - 1])));
+        }
         geo_finish(m);
     } else {
         geo_flat(m);
@@ -346,7 +353,7 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
         const double da = dD(in.a);
         if (p.bet)
             for (int a = 0; a < 3; ++a) db[a] = dD(in.b[a]);
-        for (int a = 0; a < 6; ++a) dg[a] = dD(in.g[a]);
+        for (int a = 0; a < 6; ++a) dg[a] = zero_entry<DG>(a) ? 0.0 : dD(in.g[a]);
         double Uc[NF];
         prim2con(mc, p.G, in.P, Uc);
         sources_dir<D>(p, mc, da, db, dg, in.P, Uc, acc);
@@ -364,7 +371,7 @@ __device__ __forceinline__ void flux_compute(const Params& p, const double* __re
 }
 
 // one segment per wave
-template <int D, int RECON, bool CURVED, class R, bool ACC>
+template <int D, int RECON, bool CURVED, class R, bool ACC, bool DG>
 __global__ __launch_bounds__(256) void k_flux_t(const Params p, const double* __restrict__ P,
                                                 const double* __restrict__ sig, double* __restrict__ rhs,
                                                 int nseg, long nitems) {
@@ -373,13 +380,13 @@ __global__ __launch_bounds__(256) void k_flux_t(const Params p, const double* __
     if (wid >= nitems) return;                       // uniform per wave
     const FluxItem<D> it = flux_item<D>(p, wid, nseg, lane);
     FluxIn in;
-    flux_load<D, CURVED>(p, P, sig, it, in);
-    flux_compute<D, RECON, CURVED, R, ACC>(p, P, rhs, it, in, lane);
+    flux_load<D, CURVED, DG>(p, P, sig, it, in);
+    flux_compute<D, RECON, CURVED, R, ACC, DG>(p, P, rhs, it, in, lane);
 }
 
 // persistent: one wave per SIMD walks the segments wid, wid + W, ..., loading
 // the next segment's inputs while it computes the current one
-template <int D, int RECON, bool CURVED, class R, bool ACC>
+template <int D, int RECON, bool CURVED, class R, bool ACC, bool DG>
 __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __restrict__ P,
                                                 const double* __restrict__ sig, double* __restrict__ rhs,
                                                 int nseg, long nitems) {
@@ -389,7 +396,7 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
     if (wid >= nitems) return;                       // uniform per wave
     FluxItem<D> it = flux_item<D>(p, wid, nseg, lane);
     FluxIn in;
-    flux_load<D, CURVED>(p, P, sig, it, in);
+    flux_load<D, CURVED, DG>(p, P, sig, it, in);
     // the loop begins with every input loaded on both ways into it, so the
     // wait-count pass needs no wait on them inside
     if (!ACC) wait_vm<0>();
@@ -400,8 +407,8 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
         // it then waits for the prefetch right after issuing it
         const FluxItem<D> it2 = flux_item<D>(p, nxt < nitems ? nxt : wid, nseg, lane);
         FluxIn in2;
-        flux_load<D, CURVED>(p, P, sig, it2, in2);
-        flux_compute<D, RECON, CURVED, R, ACC>(p, P, rhs, it, in, lane);
+        flux_load<D, CURVED, DG>(p, P, sig, it2, in2);
+        flux_compute<D, RECON, CURVED, R, ACC, DG>(p, P, rhs, it, in, lane);
         // the next segment's loads were followed by the NF stores of this one
         // only: wait for the loads, leave the stores in flight
         if (!ACC) wait_vm<NF>();
@@ -435,15 +442,20 @@ __device__ __forceinline__ void wait_ring() {
     asm volatile("" ::: "memory");
 }
 
+// packed index of the j-th stored metric component (DG: the diagonal only)
+template <bool DG> __host__ __device__ constexpr int gcomp(int j) { return DG ? (j == 0 ? 0 : (j == 1 ? 3 : 5)) : j; }
+
 // SHIFT: the metric has a shift (beta rows in the window); without one the
-// window holds alpha, gamma_ij and sigma only
-template <int D, int RECON, bool CURVED, class R, bool SHIFT>
+// window holds alpha, gamma_ij and sigma only.  DG: a diagonal metric, whose
+// window and staging row hold the three diagonal entries of gamma_ij
+template <int D, int RECON, bool CURVED, class R, bool SHIFT, bool DG>
 __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __restrict__ P,
                                                const double* __restrict__ sig, double* __restrict__ rhs,
                                                int seglen, int nxb, int nseg) {
     constexpr int E = (D == 1) ? 2 : 1;                 // the other transverse dimension
+    constexpr int NG = DG ? 3 : 6;                      // stored gamma_ij components
     // staging streams: sigma; alpha, gamma_ij (curved); beta^i (shift); an even count
-    constexpr int NMS = CURVED ? (SHIFT ? 12 : 8) : 2;
+    constexpr int NMS = CURVED ? ((2 + NG + (SHIFT ? 3 : 0) + 1) / 2 * 2) : 2;
     // one LDS object for the ring and the staging row: with two objects
     // filled by direct loads the wait-count pass makes every ring read wait
     // for all outstanding memory operations
@@ -485,15 +497,18 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     // wait that covers it.  (Loaded into registers, the row would be copied
     // into the window's registers right after its loads were issued, and the
     // copy would wait for every memory operation issued before it.)
-    double wa[5], wb[SHIFT ? 5 : 1][3], wg[5][6], ws[5];
+    double wa[5], wb[SHIFT ? 5 : 1][3], wg[5][NG], ws[5];
     auto load_stage = [&](int c) {
         const long ro = rowb + (long)(c + gD) * s + xpair;
         const long rs = rowb + (long)bc_map(p, D, c + gD) * s + xpair;
-        auto addr = [&](int k) -> unsigned long long {
+        auto addr = [&](int k0) -> unsigned long long {
+            // streams past the last one (an even count) repeat it
+            constexpr int nvalid = 2 + NG + (SHIFT ? 3 : 0);
+            const int k = k0 < nvalid ? k0 : nvalid - 1;
             const double* b = (!CURVED || k == 0) ? sig + rs
                             : k == 1 ? p.alp + ro
-                            : k < 8 ? p.gam + (long)(k - 2) * Np + ro
-                                    : p.bet + (long)min(k - 8, 2) * Np + ro;
+                            : k < 2 + NG ? p.gam + (long)gcomp<DG>(k - 2) * Np + ro
+                                    : p.bet + (long)(k - 2 - NG) * Np + ro;
             return (unsigned long long)b;
         };
 #pragma unroll
@@ -509,10 +524,10 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         if (CURVED) {
             ar = mst[64 + lane];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) gr[a] = mst[(2 + a) * 64 + lane];
+            for (int a = 0; a < NG; ++a) gr[a] = mst[(2 + a) * 64 + lane];
             if (SHIFT)
 #pragma unroll
-                for (int a = 0; a < 3; ++a) br[a] = mst[(8 + a) * 64 + lane];
+                for (int a = 0; a < 3; ++a) br[a] = mst[(2 + NG + a) * 64 + lane];
         }
     };
     auto bw = [&](int k, int a) { return SHIFT ? wb[SHIFT ? k : 0][a] : 0.0; };
@@ -524,7 +539,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             if (SHIFT)
                 for (int a = 0; a < 3; ++a) br[a] = p.bet[a * Np + o];
 #pragma unroll
-            for (int a = 0; a < 6; ++a) gr[a] = p.gam[a * Np + o];
+            for (int a = 0; a < NG; ++a) gr[a] = p.gam[gcomp<DG>(a) * Np + o];
         }
     };
     // window of the first step (c = c0 - 1): P rows c0-3 .. c0+1, metric rows
@@ -539,7 +554,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         double bdummy[3];
         double* bk = SHIFT ? wb[SHIFT ? k : 0] : bdummy;
         for (int a = 0; a < 3; ++a) bk[a] = 0.0;
-        for (int a = 0; a < 6; ++a) wg[k][a] = 0.0;
+        for (int a = 0; a < NG; ++a) wg[k][a] = 0.0;
         if (c >= -gD) load_metric(c, wa[k], bk, wg[k], ws[k]);
     }
 
@@ -570,16 +585,16 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         for (int f = 0; f < NF; ++f) sacc[f] = 0.0;
         if (fin && CURVED) {
             // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
-            Geo<double> ms;
+            Geo<double, DG> ms;
             ms.alp = wa[2];
             for (int a = 0; a < 3; ++a) ms.bet[a] = bw(2, a);
-            for (int a = 0; a < 6; ++a) ms.g[a] = wg[2][a];
+            for (int a = 0; a < NG; ++a) ms.g[gcomp<DG>(a)] = wg[2][a];
             geo_finish(ms);
             auto d4 = [&](double a0, double a1, double a3, double a4) { return (a0 - 8.0 * a1 + 8.0 * a3 - a4) * cd; };
             const double da = d4(wa[0], wa[1], wa[3], wa[4]);
-            double db[3], dg[6];
+            double db[3], dg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             for (int a = 0; a < 3; ++a) db[a] = d4(bw(0, a), bw(1, a), bw(3, a), bw(4, a));
-            for (int a = 0; a < 6; ++a) dg[a] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
+            for (int a = 0; a < NG; ++a) dg[gcomp<DG>(a)] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
             double Pm[NF], Um[NF];
 #pragma unroll
             for (int f = 0; f < NF; ++f) Pm[f] = ringP(c - 1, f);
@@ -590,11 +605,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         // current of c (metric and sigma row c: window 3)
         double Jc;
         {
-            Geo<double> mc;
+            Geo<double, DG> mc;
             if (CURVED) {
                 mc.alp = wa[3];
                 for (int a = 0; a < 3; ++a) mc.bet[a] = bw(3, a);
-                for (int a = 0; a < 6; ++a) mc.g[a] = wg[3][a];
+                for (int a = 0; a < NG; ++a) mc.g[gcomp<DG>(a)] = wg[3][a];
                 geo_finish(mc);
             } else {
                 geo_flat(mc);
@@ -625,14 +640,14 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         {
             // (the first step's face is not needed: computed, and stored to the ghost cell)
             // face c - 1/2: metric at the face from rows c-2 .. c+1 (window 1..4)
-            Geo<R> m;
+            Geo<R, DG> m;
             if (CURVED) {
                 auto f4 = [](double a0, double a1, double a2, double a3) {
                     return (-a0 + 9.0 * a1 + 9.0 * a2 - a3) * 0.0625;
                 };
                 m.alp = R(f4(wa[1], wa[2], wa[3], wa[4]));
                 for (int a = 0; a < 3; ++a) m.bet[a] = R(f4(bw(1, a), bw(2, a), bw(3, a), bw(4, a)));
-                for (int a = 0; a < 6; ++a) m.g[a] = R(f4(wg[1][a], wg[2][a], wg[3][a], wg[4][a]));
+                for (int a = 0; a < NG; ++a) m.g[gcomp<DG>(a)] = R(f4(wg[1][a], wg[2][a], wg[3][a], wg[4][a]));
                 geo_finish(m);
             } else {
                 geo_flat(m);
@@ -670,7 +685,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                 wa[k] = wa[k + 1];
                 if (SHIFT)
                     for (int a = 0; a < 3; ++a) wb[SHIFT ? k : 0][a] = wb[SHIFT ? k + 1 : 0][a];
-                for (int a = 0; a < 6; ++a) wg[k][a] = wg[k + 1][a];
+                for (int a = 0; a < NG; ++a) wg[k][a] = wg[k + 1][a];
             }
         }
         {
@@ -745,7 +760,8 @@ __global__ __launch_bounds__(256) void k_prim2con(const Params p, const double* 
     for (int f = 0; f < NF; ++f) U[f * p.Np + o] = Uc[f];
 }
 
-__device__ __forceinline__ void rec_setup(const Params& p, const Geo<double>& m, const double* U, RecIn& k) {
+template <bool DG>
+__device__ __forceinline__ void rec_setup(const Params& p, const Geo<double, DG>& m, const double* U, RecIn& k) {
     k.G = p.G;
     k.D = U[I_D];
     k.iD = frcp(k.D);          // used only when D > 0
@@ -757,7 +773,7 @@ __device__ __forceinline__ void rec_setup(const Params& p, const Geo<double>& m,
     for (int a = 0; a < 6; ++a) { k.g[a] = m.g[a]; k.gi[a] = m.gi[a]; }
     k.sg = m.sg;
     k.isg = m.isg;
-    lower(m.g, k.Bc, k.Bl);
+    lower(m, k.Bc, k.Bl);
     for (int i = 0; i < 3; ++i) k.Bl[i] *= m.isg;     // undensitised, lowered B
 }
 
@@ -779,11 +795,12 @@ __device__ __forceinline__ void write_prims(const Params& p, long o, const Geo<d
 
 // primitives at a recovered root from RecIn (D, Bcal) and the conserved
 // cleaning and charge values cl = (Phi, Psi, Q) of the cell
-__device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo<double>& m, const RecIn& k,
+template <bool DG>
+__device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo<double, DG>& m, const RecIn& k,
                                               const double* cl, const double* x, const double* Ec, double* P) {
     const double* v = x + 1;
     double vl[3];
-    lower(m.g, v, vl);
+    lower(m, v, vl);
     const double W = frsqrt(1.0 - dot3(vl, v));
     P[I_RHO * p.Np + o] = k.D * m.isg / W;
     P[I_P * p.Np + o] = x[0];
@@ -860,27 +877,37 @@ __device__ __forceinline__ void metric_derivs(const Params& p, long o, MetricDer
 // d, so the derivative costs four lane shuffles per field); the stage kernels
 // add sources_local.  R: double, or the dual type of the adjoint's passes.
 
+// component i of gamma^ij A_j (i from an unrolled loop)
+template <bool DG> __device__ __forceinline__ double raise1i(const Geo<double, DG>& m, int i, const double* A) {
+    if constexpr (DG) return m.gi[sidx(i, i)] * A[i];
+    else return m.gi[sidx(i, 0)] * A[0] + m.gi[sidx(i, 1)] * A[1] + m.gi[sidx(i, 2)] * A[2];
+}
+
 // densitised stress S^{jk} (both indices up) of a cell state
-template <class R>
-__device__ __forceinline__ void stress_up(const Params& p, const Geo<double>& m, const R* Pc, R* Su) {
+template <class R, bool DG>
+__device__ __forceinline__ void stress_up(const Params& p, const Geo<double, DG>& m, const R* Pc, R* Su) {
     const R* v = Pc + I_V;
     const R* B = Pc + I_B;
     const R* E = Pc + I_E;
     R vl[3], Bl[3], El[3];
-    lower(m.g, v, vl);
-    lower(m.g, B, Bl);
-    lower(m.g, E, El);
+    lower(m, v, vl);
+    lower(m, B, Bl);
+    lower(m, E, El);
     const R W = frsqrt(R(1.0) - dot3(vl, v));
     const R hW2 = (Pc[I_RHO] + Pc[I_P] * (p.G / (p.G - 1.0))) * (W * W);
     const R pt = Pc[I_P] + (dot3(El, E) + dot3(Bl, B)) * 0.5;
     for (int j = 0; j < 3; ++j)
-        for (int kk = j; kk < 3; ++kk)
-            Su[sidx(j, kk)] = (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk] + pt * m.gi[sidx(j, kk)]) * m.sg;
+        for (int kk = j; kk < 3; ++kk) {
+            if (zero_entry<DG>(sidx(j, kk)))
+                Su[sidx(j, kk)] = (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk]) * m.sg;
+            else
+                Su[sidx(j, kk)] = (hW2 * v[j] * v[kk] - E[j] * E[kk] - B[j] * B[kk] + pt * m.gi[sidx(j, kk)]) * m.sg;
+        }
 }
 
 // S = the terms without metric derivatives (K: extrinsic curvature, used if hasK)
-template <bool CURVED, class R>
-__device__ __forceinline__ void sources_local(const Params& p, const Geo<double>& m, const double (&K)[6], bool hasK,
+template <bool CURVED, class R, bool DG>
+__device__ __forceinline__ void sources_local(const Params& p, const Geo<double, DG>& m, const double (&K)[6], bool hasK,
                                               const R* Pc, const R* Uc, R* S) {
     const R* v = Pc + I_V;
     const double kap = p.kappa;
@@ -900,7 +927,7 @@ __device__ __forceinline__ void sources_local(const Params& p, const Geo<double>
         for (int i = 0; i < 3; ++i)
             for (int j = 0; j < 3; ++j) {
                 const double kij = K[sidx(i, j)];
-                Ktr += m.gi[sidx(i, j)] * kij;
+                if (!zero_entry<DG>(sidx(i, j))) Ktr += m.gi[sidx(i, j)] * kij;
                 SK += Su[sidx(i, j)] * kij;
             }
     }
@@ -913,8 +940,9 @@ __device__ __forceinline__ void sources_local(const Params& p, const Geo<double>
 // S += the terms with the derivatives along d: da = d_d alpha, db[i] =
 // d_d beta^i, dg[jk] = d_d gamma_jk.  Gamma^i = gamma^il A_l with
 // A_l = gamma^jk d_j gamma_lk - 1/2 gamma^jk d_l gamma_jk.
-template <int d, class R>
-__device__ __forceinline__ void sources_dir(const Params& p, const Geo<double>& m, double da, const double* db,
+// (DG: dg and the inverse metric are diagonal, their zero entries are skipped)
+template <int d, class R, bool DG>
+__device__ __forceinline__ void sources_dir(const Params& p, const Geo<double, DG>& m, double da, const double* db,
                                             const double* dg, const R* Pc, const R* Uc, R* S) {
     const double a = m.alp;
     R Su[6];
@@ -923,22 +951,25 @@ __device__ __forceinline__ void sources_dir(const Params& p, const Geo<double>& 
     double A[3];
     double tr = 0.0;
     for (int j = 0; j < 3; ++j)
-        for (int kk = 0; kk < 3; ++kk) tr += m.gi[sidx(j, kk)] * dg[sidx(j, kk)];
+        for (int kk = 0; kk < 3; ++kk)
+            if (!zero_entry<DG>(sidx(j, kk))) tr += m.gi[sidx(j, kk)] * dg[sidx(j, kk)];
     for (int l = 0; l < 3; ++l) {
         double s1 = 0.0;
-        for (int kk = 0; kk < 3; ++kk) s1 += m.gi[sidx(d, kk)] * dg[sidx(l, kk)];
+        for (int kk = 0; kk < 3; ++kk)
+            if (!zero_entry<DG>(sidx(d, kk)) && !zero_entry<DG>(sidx(l, kk))) s1 += m.gi[sidx(d, kk)] * dg[sidx(l, kk)];
         A[l] = s1 - (l == d ? 0.5 * tr : 0.0);
     }
     const R* Sl = Uc + I_S;
     R t = R(0.0);
     for (int j = 0; j < 3; ++j)
-        for (int kk = 0; kk < 3; ++kk) t += Su[sidx(j, kk)] * dg[sidx(j, kk)];
+        for (int kk = 0; kk < 3; ++kk)
+            if (!zero_entry<DG>(sidx(j, kk))) t += Su[sidx(j, kk)] * dg[sidx(j, kk)];
     S[I_S + d] += t * (0.5 * a) + (Sl[0] * db[0] + Sl[1] * db[1] + Sl[2] * db[2]) - (Uc[I_TAU] + Uc[I_D]) * da;
-    const R Supd = Sl[0] * m.gi[sidx(d, 0)] + Sl[1] * m.gi[sidx(d, 1)] + Sl[2] * m.gi[sidx(d, 2)];
+    const R Supd = raise1<d>(m, Sl);
     S[I_TAU] += -(Supd * da);
     for (int i = 0; i < 3; ++i) {
-        const double Gm = m.gi[sidx(i, 0)] * A[0] + m.gi[sidx(i, 1)] * A[1] + m.gi[sidx(i, 2)] * A[2];
-        const double gg = m.gi[sidx(i, d)] * da - a * Gm;
+        const double Gm = raise1i(m, i, A);
+        const double gg = zero_entry<DG>(sidx(i, d)) ? -(a * Gm) : m.gi[sidx(i, d)] * da - a * Gm;
         S[I_B + i] += Uc[I_PHI] * gg - Uc[I_B + d] * db[i];
         S[I_E + i] += Uc[I_PSI] * gg - Uc[I_E + d] * db[i];
     }
@@ -995,7 +1026,7 @@ struct StreamList {
     int n;
     int s[80];                                   // array * 32 + field
 };
-template <int STAGE, bool CURVED, bool HASK> __host__ __device__ constexpr StreamList stage_streams() {
+template <int STAGE, bool CURVED, bool HASK, bool DG> __host__ __device__ constexpr StreamList stage_streams() {
     StreamList L{0, {}};
     auto add = [&L](int a, int f) { L.s[L.n++] = a * 32 + f; };
     for (int f = 0; f < NF; ++f) add(SA_UN, f);
@@ -1019,7 +1050,8 @@ template <int STAGE, bool CURVED, bool HASK> __host__ __device__ constexpr Strea
     }
     if (CURVED) {
         add(SA_ALP, 0);
-        for (int a = 0; a < 6; ++a) add(SA_GAM, a);
+        for (int a = 0; a < 6; ++a)
+            if (!zero_entry<DG>(a)) add(SA_GAM, a);
         if (STAGE != 1 && HASK)
             for (int a = 0; a < 6; ++a) add(SA_K, a);
     }
@@ -1027,8 +1059,8 @@ template <int STAGE, bool CURVED, bool HASK> __host__ __device__ constexpr Strea
     return L;
 }
 // position of stream (a, f) in the list (-1: not there)
-template <int STAGE, bool CURVED, bool HASK> __device__ constexpr int stream_pos(int a, int f) {
-    constexpr StreamList L = stage_streams<STAGE, CURVED, HASK>();
+template <int STAGE, bool CURVED, bool HASK, bool DG> __device__ constexpr int stream_pos(int a, int f) {
+    constexpr StreamList L = stage_streams<STAGE, CURVED, HASK, DG>();
     for (int i = 0; i < L.n; ++i)
         if (L.s[i] == a * 32 + f) return i;
     return -1;
@@ -1064,10 +1096,10 @@ __device__ __forceinline__ Chunk chunk_at(const Params& p, long q, int nsx) {
 // (global_load_lds_dwordx4: lane m brings cells 2(m mod 32), +1 of stream
 // 2i + m / 32; the pair is clamped inside the padded row, a pair past the
 // row's end is never read).
-template <int STAGE, bool CURVED, bool HASK>
+template <int STAGE, bool CURVED, bool HASK, bool DG>
 __device__ __forceinline__ void stage_issue(const Params& p, const StageArrays& A, const Chunk& c, double* buf,
                                             int lane) {
-    constexpr StreamList L = stage_streams<STAGE, CURVED, HASK>();
+    constexpr StreamList L = stage_streams<STAGE, CURVED, HASK, DG>();
     const long xp = min((long)(c.x0 + 2 * (lane & 31)), (long)(p.np[0] - 2 - p.g[0]));
     const long oo = c.orow + xp;
     const bool hi = lane >= 32;
@@ -1085,13 +1117,13 @@ __device__ __forceinline__ void stage_issue(const Params& p, const StageArrays& 
 
 // The lane's inputs from the LDS buffer.  A lane past the row's end reads the
 // row's last cell (ok = false): it repeats that cell's arithmetic and stores.
-template <int STAGE, bool CURVED, bool HASK>
+template <int STAGE, bool CURVED, bool HASK, bool DG>
 __device__ __forceinline__ void stage_read(const Params& p, const Chunk& c, const double* buf, int lane, StageIn& in) {
     in.ok = c.x0 + lane < p.n[0];
     const int lc = in.ok ? lane : p.n[0] - 1 - c.x0;
     in.o = c.orow + c.x0 + lc;
     auto rd = [&](int a, int f) -> double {
-        const int i = stream_pos<STAGE, CURVED, HASK>(a, f);
+        const int i = stream_pos<STAGE, CURVED, HASK, DG>(a, f);
         return i < 0 ? 0.0 : buf[i * 64 + lc];
     };
 #pragma unroll
@@ -1119,11 +1151,12 @@ __device__ __forceinline__ void stage_read(const Params& p, const Chunk& c, cons
 }
 
 // (the shift enters the stage kernels nowhere: the flux kernels carry it)
-template <bool CURVED> __device__ __forceinline__ void stage_geo(const StageIn& in, Geo<double>& m) {
+template <bool CURVED, bool DG> __device__ __forceinline__ void stage_geo(const StageIn& in, Geo<double, DG>& m) {
     if (CURVED) {
         m.alp = in.a;
         for (int a = 0; a < 3; ++a) m.bet[a] = 0.0;
-        for (int a = 0; a < 6; ++a) m.g[a] = in.g[a];
+        for (int a = 0; a < 6; ++a)
+            if (!zero_entry<DG>(a)) m.g[a] = in.g[a];
         geo_finish(m);
     } else {
         geo_flat(m);
@@ -1133,12 +1166,12 @@ template <bool CURVED> __device__ __forceinline__ void stage_geo(const StageIn& 
 // stage 1: E(1) = E^n + gamma dt R_E(U(1)), everything else unchanged.  A
 // failed cell (flagged in status and the failure count) is written as the
 // primitives of U^n at the guess's p and v with E = E^n.
-template <bool CURVED>
+template <bool CURVED, bool DG>
 __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ P1,
                                             double* __restrict__ R1, double* __restrict__ U1,
                                             int* __restrict__ status, long st_stride, StageTally& tal) {
     const long Np = p.Np, o = in.o;
-    Geo<double> m;
+    Geo<double, DG> m;
     stage_geo<CURVED>(in, m);
     RecIn k;
     rec_setup(p, m, in.Un, k);
@@ -1169,12 +1202,12 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
 
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
 // divergence (with the metric-derivative sources) of P_s is in rhs
-template <int STAGE, bool CURVED, bool HASK>
+template <int STAGE, bool CURVED, bool HASK, bool DG>
 __device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
                                             double* __restrict__ Po, double* __restrict__ Ro,
                                             int* __restrict__ status, long st_stride, StageTally& tal) {
     const long Np = p.Np, o = in.o;
-    Geo<double> m;
+    Geo<double, DG> m;
     stage_geo<CURVED>(in, m);
     const double g = GAM_IMEX();
     RecIn k;
@@ -1269,7 +1302,7 @@ template <int STAGE> constexpr int stage_stores() { return STAGE == 1 ? 18 : (ST
 // into registers first) is computed and stored; the wait for them leaves the
 // current chunk's stores in flight (stage 1 stores 18 or 32 per chunk, so
 // waiting for 18 is safe in both cases).
-template <int STAGE, bool CURVED, bool HASK>
+template <int STAGE, bool CURVED, bool HASK, bool DG>
 __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const double* __restrict__ sig,
                                               const double* __restrict__ Un, const double* __restrict__ Us,
                                               const double* __restrict__ Ps, const double* __restrict__ R1,
@@ -1277,7 +1310,7 @@ __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const d
                                               double* __restrict__ Uo, double* __restrict__ Po,
                                               double* __restrict__ Ro, int* __restrict__ status, long st_stride,
                                               unsigned long long* nfail) {
-    constexpr int NS = stage_streams<STAGE, CURVED, HASK>().n;
+    constexpr int NS = stage_streams<STAGE, CURVED, HASK, DG>().n;
     static_assert(NS <= 80 && NS % 2 == 0, "stream list");
     __shared__ double buf[NS * 64];
     __shared__ StageTally tal;
@@ -1292,18 +1325,18 @@ __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const d
     long q = xcd_block();
     if (q < nchunk) {                                          // uniform per wave
         Chunk c = chunk_at(p, q, nsx);
-        stage_issue<STAGE, CURVED, HASK>(p, A, c, buf, lane);
+        stage_issue<STAGE, CURVED, HASK, DG>(p, A, c, buf, lane);
         wait_vm<0>();
         for (;;) {
             StageIn in;
-            stage_read<STAGE, CURVED, HASK>(p, c, buf, lane, in);
+            stage_read<STAGE, CURVED, HASK, DG>(p, c, buf, lane, in);
             wait_lgkm0();                                      // the buffer is free again
             const long qn = q + W;
             const Chunk cn = chunk_at(p, qn < nchunk ? qn : q, nsx);
             // unconditional (the last pass reloads its own chunk)
-            stage_issue<STAGE, CURVED, HASK>(p, A, cn, buf, lane);
-            if (STAGE == 1) stage1_cell<CURVED>(p, dt, in, Po, Ro, Uo, status, st_stride, tal);
-            else update_cell<STAGE, CURVED, HASK>(p, dt, in, Uo, Po, Ro, status, st_stride, tal);
+            stage_issue<STAGE, CURVED, HASK, DG>(p, A, cn, buf, lane);
+            if (STAGE == 1) stage1_cell<CURVED, DG>(p, dt, in, Po, Ro, Uo, status, st_stride, tal);
+            else update_cell<STAGE, CURVED, HASK, DG>(p, dt, in, Uo, Po, Ro, status, st_stride, tal);
             // the loads above were followed by this chunk's stores only
             wait_vm<stage_stores<STAGE>()>();
             if (qn >= nchunk) break;

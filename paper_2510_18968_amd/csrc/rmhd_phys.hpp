@@ -48,12 +48,19 @@ __host__ __device__ constexpr int sidx(int i, int j) {
     return (i == j) ? (i == 0 ? 0 : (i == 1 ? 3 : 5)) : ((i + j == 1) ? 1 : ((i + j == 2) ? 2 : 4));
 }
 
-// 3-metric at one point with the quantities derived from it (Sec. II.A)
-template <class R> struct Geo {
+// 3-metric at one point with the quantities derived from it (Sec. II.A).
+// DG: the metric is diagonal (gamma_xy = gamma_xz = gamma_yz = 0, e.g.
+// conformally flat); its off-diagonal entries are held as zero and the
+// contractions below skip them.
+template <class R, bool DG = false> struct Geo {
+    static constexpr bool diag = DG;
     R alp, bet[3], g[6], gi[6], sg, isg;
 };
 
-template <class R> __device__ __forceinline__ void geo_flat(Geo<R>& m) {
+// packed symmetric index a is an entry a diagonal metric holds as zero
+template <bool DG> __host__ __device__ constexpr bool zero_entry(int a) { return DG && (a == 1 || a == 2 || a == 4); }
+
+template <class R, bool DG> __device__ __forceinline__ void geo_flat(Geo<R, DG>& m) {
     m.alp = R(1);
     m.bet[0] = m.bet[1] = m.bet[2] = R(0);
     m.g[0] = m.g[3] = m.g[5] = R(1);
@@ -62,8 +69,23 @@ template <class R> __device__ __forceinline__ void geo_flat(Geo<R>& m) {
     m.sg = m.isg = R(1);
 }
 
-// inverse by cofactors and sqrt(det); m.g already set
-template <class R> __device__ __forceinline__ void geo_finish(Geo<R>& m) {
+// inverse by cofactors and sqrt(det); m.g already set (its diagonal, for DG)
+template <class R, bool DG> __device__ __forceinline__ void geo_finish(Geo<R, DG>& m) {
+    if constexpr (DG) {
+        const R gxx = m.g[0], gyy = m.g[3], gzz = m.g[5];
+        m.g[1] = m.g[2] = m.g[4] = R(0);
+        const R cxx = gyy * gzz;
+        const R det = gxx * cxx;
+        const R rs = frsqrt(det);
+        const R id = rs * rs;
+        m.gi[0] = cxx * id;
+        m.gi[1] = m.gi[2] = m.gi[4] = R(0);
+        m.gi[3] = (gxx * gzz) * id;
+        m.gi[5] = (gxx * gyy) * id;
+        m.sg = det * rs;
+        m.isg = rs;
+        return;
+    }
     const R gxx = m.g[0], gxy = m.g[1], gxz = m.g[2], gyy = m.g[3], gyz = m.g[4], gzz = m.g[5];
     const R cxx = gyy * gzz - gyz * gyz;
     const R cxy = gxz * gyz - gxy * gzz;
@@ -86,6 +108,21 @@ template <class M, class R> __device__ __forceinline__ void lower(const M* g, co
     l[1] = g[1] * u[0] + g[3] * u[1] + g[4] * u[2];
     l[2] = g[2] * u[0] + g[4] * u[1] + g[5] * u[2];
 }
+// gamma_ij u^j
+template <class M, bool DG, class R> __device__ __forceinline__ void lower(const Geo<M, DG>& m, const R* u, R* l) {
+    if constexpr (DG) {
+        l[0] = m.g[0] * u[0];
+        l[1] = m.g[3] * u[1];
+        l[2] = m.g[5] * u[2];
+    } else {
+        lower(m.g, u, l);
+    }
+}
+// component D of gamma^ij l_j
+template <int D, class M, bool DG, class R> __device__ __forceinline__ R raise1(const Geo<M, DG>& m, const R* l) {
+    if constexpr (DG) return l[D] * m.gi[sidx(D, D)];
+    else return l[0] * m.gi[sidx(D, 0)] + l[1] * m.gi[sidx(D, 1)] + l[2] * m.gi[sidx(D, 2)];
+}
 template <class R> __device__ __forceinline__ R dot3(const R* a, const R* b) {
     return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
@@ -97,14 +134,15 @@ template <class R> __device__ __forceinline__ void cross(const R* a, const R* b,
 }
 
 // ---------------------------------------------------------------- prim2con
-template <class M, class R> __device__ __forceinline__ void prim2con(const Geo<M>& m, R G, const R* P, R* U) {
+template <class M, bool DG, class R>
+__device__ __forceinline__ void prim2con(const Geo<M, DG>& m, R G, const R* P, R* U) {
     const R* v = P + I_V;
     const R* B = P + I_B;
     const R* E = P + I_E;
     R vl[3], Bl[3], El[3], c[3];
-    lower(m.g, v, vl);
-    lower(m.g, B, Bl);
-    lower(m.g, E, El);
+    lower(m, v, vl);
+    lower(m, B, Bl);
+    lower(m, E, El);
     const R W = frsqrt(R(1) - dot3(vl, v));
     const R W2 = W * W;
     const R hW2 = (P[I_RHO] + G / (G - R(1)) * P[I_P]) * W2;
@@ -119,11 +157,12 @@ template <class M, class R> __device__ __forceinline__ void prim2con(const Geo<M
 
 // densitised current of eq. Ohm_law at a point:
 // J^i = Q v^i + W sigma [Ecal^i + (v_l x B_l)^i - (v_l . Ecal) v^i]
-template <class M, class R> __device__ __forceinline__ void current(const Geo<M>& m, const R* P, R sigma, R* J) {
+template <class M, bool DG, class R>
+__device__ __forceinline__ void current(const Geo<M, DG>& m, const R* P, R sigma, R* J) {
     const R* v = P + I_V;
     R vl[3], Bl[3], vb[3];
-    lower(m.g, v, vl);
-    lower(m.g, P + I_B, Bl);
+    lower(m, v, vl);
+    lower(m, P + I_B, Bl);
     cross(vl, Bl, vb);
     const R W = frsqrt(R(1) - dot3(vl, v));
     const R Ec[3] = {P[I_E] * m.sg, P[I_E + 1] * m.sg, P[I_E + 2] * m.sg};
@@ -135,15 +174,15 @@ template <class M, class R> __device__ __forceinline__ void current(const Geo<M>
 // conserved variables and physical flux along D of one state (eqs.
 // conserved_*, GRRMHD_flux_form with sqrt(gamma) counted once); Jd is the
 // current carried by the charge flux at this face
-template <int D, class M, class R>
-__device__ __forceinline__ void state_flux(const Geo<M>& m, R G, const R* P, R Jd, R* U, R* F) {
+template <int D, class M, bool DG, class R>
+__device__ __forceinline__ void state_flux(const Geo<M, DG>& m, R G, const R* P, R Jd, R* U, R* F) {
     const R* v = P + I_V;
     const R* B = P + I_B;
     const R* E = P + I_E;
     R vl[3], Bl[3], El[3], c[3];
-    lower(m.g, v, vl);
-    lower(m.g, B, Bl);
-    lower(m.g, E, El);
+    lower(m, v, vl);
+    lower(m, B, Bl);
+    lower(m, E, El);
     const R W = frsqrt(R(1) - dot3(vl, v));
     const R hW2 = (P[I_RHO] + G / (G - R(1)) * P[I_P]) * (W * W);
     const R em = R(0.5) * (dot3(El, E) + dot3(Bl, B));
@@ -160,7 +199,7 @@ __device__ __forceinline__ void state_flux(const Geo<M>& m, R G, const R* P, R J
     F[I_D] = (a * vd - bd) * Dd;
     for (int i = 0; i < 3; ++i)
         F[I_S + i] = as * (hW2 * vd * vl[i] - Ed * El[i] - Bd * Bl[i] + (i == D ? pt : R(0))) - bd * U[I_S + i];
-    const R Sd = U[I_S] * m.gi[sidx(D, 0)] + U[I_S + 1] * m.gi[sidx(D, 1)] + U[I_S + 2] * m.gi[sidx(D, 2)];
+    const R Sd = raise1<D>(m, U + I_S);
     F[I_TAU] = a * (Sd - vd * Dd) - bd * U[I_TAU];
     // (e_D x X)^i for covariant X
     R eE[3], eB[3];
@@ -168,9 +207,14 @@ __device__ __forceinline__ void state_flux(const Geo<M>& m, R G, const R* P, R J
     if (D == 1) { eE[0] = El[2]; eE[1] = R(0); eE[2] = -El[0]; eB[0] = Bl[2]; eB[1] = R(0); eB[2] = -Bl[0]; }
     if (D == 2) { eE[0] = -El[1]; eE[1] = El[0]; eE[2] = R(0); eB[0] = -Bl[1]; eB[1] = Bl[0]; eB[2] = R(0); }
     for (int i = 0; i < 3; ++i) {
-        const M gid = m.gi[sidx(i, D)];
-        F[I_B + i] = a * (eE[i] + gid * U[I_PHI]) - bd * U[I_B + i];
-        F[I_E + i] = -a * (eB[i] - gid * U[I_PSI]) - bd * U[I_E + i];
+        if (zero_entry<DG>(sidx(i, D))) {
+            F[I_B + i] = a * eE[i] - bd * U[I_B + i];
+            F[I_E + i] = -a * eB[i] - bd * U[I_E + i];
+        } else {
+            const M gid = m.gi[sidx(i, D)];
+            F[I_B + i] = a * (eE[i] + gid * U[I_PHI]) - bd * U[I_B + i];
+            F[I_E + i] = -a * (eB[i] - gid * U[I_PSI]) - bd * U[I_E + i];
+        }
     }
     F[I_PHI] = a * U[I_B + D] - bd * U[I_PHI];
     F[I_PSI] = a * U[I_E + D] - bd * U[I_PSI];

@@ -1,29 +1,34 @@
 // Instantiates every stage kernel, the FP64 x-flux kernels and y/z window
-// kernels so that their
-// gfx950 assembly can be checked
-// (tests/test_stage_waits.py); never linked into the library.
+// kernels (general and diagonal metric) so that their gfx950 assembly can be
+// checked (tests/test_stage_waits.py); never linked into the library.
 #include <hip/hip_runtime.h>
 #include "rmhd_kernels.hpp"
 using namespace rmhd;
-template <int S, bool C, bool K> void inst(const Params& p, double* a, unsigned long long* c, int* s) {
-    k_stage<S, C, K><<<1, 64>>>(p, 0.1, a, a, a, a, a, a, a, a, a, a, s, 1L, c);
+template <int S, bool C, bool K, bool DG> void inst(const Params& p, double* a, unsigned long long* c, int* s) {
+    k_stage<S, C, K, DG><<<1, 64>>>(p, 0.1, a, a, a, a, a, a, a, a, a, a, s, 1L, c);
 }
-template <int RC, bool C> void inst_x(const Params& p, double* a) {
-    k_flux_p<0, RC, C, double, false><<<8, 256>>>(p, a, a, a, 1, 1L);
+template <int RC, bool C, bool DG> void inst_x(const Params& p, double* a) {
+    k_flux_p<0, RC, C, double, false, DG><<<8, 256>>>(p, a, a, a, 1, 1L);
 }
-template <int D, int RC, bool C, class R, bool SH> void inst_w(const Params& p, double* a) {
-    k_flux_w<D, RC, C, R, SH><<<8, 64>>>(p, a, a, a, 32, 1, 1);
+template <int D, int RC, bool C, class R, bool SH, bool DG> void inst_w(const Params& p, double* a) {
+    k_flux_w<D, RC, C, R, SH, DG><<<8, 64>>>(p, a, a, a, 32, 1, 1);
 }
 void all_w(const Params& p, double* a) {
-    inst_w<1, 2, true, double, false>(p, a); inst_w<2, 2, true, double, false>(p, a);
-    inst_w<1, 1, true, double, false>(p, a); inst_w<2, 0, false, double, false>(p, a);
-    inst_w<1, 2, true, float, false>(p, a); inst_w<2, 2, true, float, false>(p, a);
-    inst_w<1, 2, true, double, true>(p, a); inst_w<2, 1, true, float, true>(p, a);
+    inst_w<1, 2, true, double, false, false>(p, a); inst_w<2, 2, true, double, false, false>(p, a);
+    inst_w<1, 1, true, double, false, false>(p, a); inst_w<2, 0, false, double, false, false>(p, a);
+    inst_w<1, 2, true, float, false, false>(p, a); inst_w<2, 2, true, float, false, false>(p, a);
+    inst_w<1, 2, true, double, true, false>(p, a); inst_w<2, 1, true, float, true, false>(p, a);
+    inst_w<1, 2, true, double, false, true>(p, a); inst_w<2, 2, true, double, false, true>(p, a);
+    inst_w<1, 2, true, float, false, true>(p, a); inst_w<2, 1, true, double, true, true>(p, a);
+}
+template <int S> void stages(const Params& p, double* a, unsigned long long* c, int* s) {
+    inst<S, false, false, false>(p, a, c, s);
+    inst<S, true, false, false>(p, a, c, s); inst<S, true, true, false>(p, a, c, s);
+    inst<S, true, false, true>(p, a, c, s); inst<S, true, true, true>(p, a, c, s);
 }
 void all(const Params& p, double* a, unsigned long long* c, int* s) {
-    inst_x<0, false>(p, a); inst_x<1, false>(p, a); inst_x<2, false>(p, a);
-    inst_x<0, true>(p, a); inst_x<1, true>(p, a); inst_x<2, true>(p, a);
-    inst<1, false, false>(p, a, c, s); inst<1, true, false>(p, a, c, s); inst<1, true, true>(p, a, c, s);
-    inst<2, false, false>(p, a, c, s); inst<2, true, false>(p, a, c, s); inst<2, true, true>(p, a, c, s);
-    inst<3, false, false>(p, a, c, s); inst<3, true, false>(p, a, c, s); inst<3, true, true>(p, a, c, s);
+    inst_x<0, false, false>(p, a); inst_x<1, false, false>(p, a); inst_x<2, false, false>(p, a);
+    inst_x<0, true, false>(p, a); inst_x<1, true, false>(p, a); inst_x<2, true, false>(p, a);
+    inst_x<0, true, true>(p, a); inst_x<1, true, true>(p, a); inst_x<2, true, true>(p, a);
+    stages<1>(p, a, c, s); stages<2>(p, a, c, s); stages<3>(p, a, c, s);
 }
