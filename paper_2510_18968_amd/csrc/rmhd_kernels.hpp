@@ -564,9 +564,12 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     // so the wait for a ring row can leave everything issued after it in flight
     constexpr int NMET = NMS / 2;
     const long odummy = rowb + p.g[0] - 1;               // an x ghost of rhs: written, never read
-    R PLc[NF], Fprev[NF];
+    // part: row c - 1 without its upper face, i.e. the lower face's flux over
+    // dx (left by the previous step) plus the sources of c - 1
+    R PLc[NF];
+    double part[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) { PLc[f] = R(0); Fprev[f] = R(0); }
+    for (int f = 0; f < NF; ++f) { PLc[f] = R(0); part[f] = 0.0; }
     double Jprev = 0.0;
     // everything of the first window has landed before the loop: on both ways
     // into the loop head the wait-count pass then sees the same loads pending
@@ -576,13 +579,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         const int cnext = min(c + 3, nD + 2);           // row c + 3, clamped inside the padding
         const bool fin = c - 1 >= c0;                   // rhs of c - 1 is finished this step
         const long om = base + (long)(c - 1 + gD) * s;
-        double acc[NF], sacc[NF];
+        double acc[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f] = rhs[f * Np + om];
-        // the sources go to their own sum: acc is first used at the store,
+        // the sources go to the partial sum: acc is first used at the store,
         // so its loads have the whole step to land
-#pragma unroll
-        for (int f = 0; f < NF; ++f) sacc[f] = 0.0;
         if (fin && CURVED) {
             // sources of c - 1: metric rows c-3 .. c+1 (window 0..4), P row c - 1
             Geo<double, DG> ms;
@@ -599,7 +600,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
 #pragma unroll
             for (int f = 0; f < NF; ++f) Pm[f] = ringP(c - 1, f);
             prim2con(ms, p.G, Pm, Um);
-            sources_dir<D>(p, ms, da, db, dg, Pm, Um, sacc);
+            sources_dir<D>(p, ms, da, db, dg, Pm, Um, part);
         }
         __builtin_amdgcn_sched_barrier(0);
         // current of c (metric and sigma row c: window 3)
@@ -667,9 +668,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             wait_vm<NF / 2>();
             const long os = (fin && valid) ? om : odummy + (long)(c - 1 + gD) * s;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) rhs[f * Np + os] = acc[f] + (sacc[f] + double(-(Fh[f] - Fprev[f]) * ih));
-#pragma unroll
-            for (int f = 0; f < NF; ++f) Fprev[f] = Fh[f];
+            for (int f = 0; f < NF; ++f) {
+                const double fo = double(Fh[f] * ih);
+                rhs[f * Np + os] = acc[f] + (part[f] - fo);
+                part[f] = fo;
+            }
         }
 #pragma unroll
         for (int f = 0; f < NF; ++f) PLc[f] = fp[f];
@@ -761,7 +764,8 @@ __global__ __launch_bounds__(256) void k_prim2con(const Params p, const double* 
 }
 
 template <bool DG>
-__device__ __forceinline__ void rec_setup(const Params& p, const Geo<double, DG>& m, const double* U, RecIn& k) {
+__device__ __forceinline__ void rec_setup(const Params& p, const Geo<double, DG>& m, const double* U,
+                                          RecInT<double, DG>& k) {
     k.G = p.G;
     k.D = U[I_D];
     k.iD = frcp(k.D);          // used only when D > 0
@@ -796,7 +800,8 @@ __device__ __forceinline__ void write_prims(const Params& p, long o, const Geo<d
 // primitives at a recovered root from RecIn (D, Bcal) and the conserved
 // cleaning and charge values cl = (Phi, Psi, Q) of the cell
 template <bool DG>
-__device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo<double, DG>& m, const RecIn& k,
+__device__ __forceinline__ void write_prims_k(const Params& p, long o, const Geo<double, DG>& m,
+                                              const RecInT<double, DG>& k,
                                               const double* cl, const double* x, const double* Ec, double* P) {
     const double* v = x + 1;
     double vl[3];
@@ -1173,7 +1178,7 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
     const long Np = p.Np, o = in.o;
     Geo<double, DG> m;
     stage_geo<CURVED>(in, m);
-    RecIn k;
+    RecInT<double, DG> k;
     rec_setup(p, m, in.Un, k);
     for (int i = 0; i < 3; ++i) k.Es[i] = in.Un[I_E + i];
     if (U1)
@@ -1210,7 +1215,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     Geo<double, DG> m;
     stage_geo<CURVED>(in, m);
     const double g = GAM_IMEX();
-    RecIn k;
+    RecInT<double, DG> k;
     double x[4] = {in.P[I_P], in.P[I_V], in.P[I_V + 1], in.P[I_V + 2]};
     double cl[3];
     double YD;

@@ -552,7 +552,8 @@ __device__ __forceinline__ D1 fmax(const D1& a, const D1& b) { return a.v >= b.v
 
 // inputs of one recovery (T = double, or a dual type when the adjoint
 // differentiates the recovered state with respect to them)
-template <class T> struct RecInT {
+template <class T, bool DG = false> struct RecInT {
+    static constexpr bool diag = DG;                 // a diagonal 3-metric (zero entries skipped)
     double G;
     T D, tau, S[3], Bc[3], Bl[3], Es[3], cfac;   // cfac = a dt alpha sigma; Bl = lowered B / sqrt(gamma)
     T iD;                                        // 1 / D
@@ -572,7 +573,10 @@ __device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eo
     const S p = x[0];
     const S v[3] = {x[1], x[2], x[3]};
     S vl[3];
-    for (int i = 0; i < 3; ++i) vl[i] = k.g[sidx(i, 0)] * v[0] + k.g[sidx(i, 1)] * v[1] + k.g[sidx(i, 2)] * v[2];
+    for (int i = 0; i < 3; ++i) {
+        if constexpr (K::diag) vl[i] = k.g[sidx(i, i)] * v[i];
+        else vl[i] = k.g[sidx(i, 0)] * v[0] + k.g[sidx(i, 1)] * v[1] + k.g[sidx(i, 2)] * v[2];
+    }
     const S v2 = vl[0] * v[0] + vl[1] * v[1] + vl[2] * v[2];
     if (!(val(v2) < 1.0) || !(val(p) > 0.0)) return false;
     const S W = rsq(1.0 - v2);
@@ -591,7 +595,10 @@ __device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eo
     S E[3];
     for (int i = 0; i < 3; ++i) E[i] = (b[i] + c * vE * v[i]) * i1c;
     S El[3];
-    for (int i = 0; i < 3; ++i) El[i] = k.g[sidx(i, 0)] * E[0] + k.g[sidx(i, 1)] * E[1] + k.g[sidx(i, 2)] * E[2];
+    for (int i = 0; i < 3; ++i) {
+        if constexpr (K::diag) El[i] = k.g[sidx(i, i)] * E[i];
+        else El[i] = k.g[sidx(i, 0)] * E[0] + k.g[sidx(i, 1)] * E[1] + k.g[sidx(i, 2)] * E[2];
+    }
     const S em = (El[0] * E[0] + El[1] * E[1] + El[2] * E[2] +
                   (k.Bl[0] * k.Bc[0] + k.Bl[1] * k.Bc[1] + k.Bl[2] * k.Bc[2]) * k.sg) * (0.5 * k.isg);
     const S den = k.tau + k.D + k.sg * p - em;
@@ -601,7 +608,10 @@ __device__ __forceinline__ bool rec_residual(const K& k, const S* x, S* r, S* Eo
     wl[1] = (k.S[1] - (E[2] * k.Bc[0] - E[0] * k.Bc[2])) * iden;
     wl[2] = (k.S[2] - (E[0] * k.Bc[1] - E[1] * k.Bc[0])) * iden;
     S w[3];
-    for (int i = 0; i < 3; ++i) w[i] = k.gi[sidx(i, 0)] * wl[0] + k.gi[sidx(i, 1)] * wl[1] + k.gi[sidx(i, 2)] * wl[2];
+    for (int i = 0; i < 3; ++i) {
+        if constexpr (K::diag) w[i] = k.gi[sidx(i, i)] * wl[i];
+        else w[i] = k.gi[sidx(i, 0)] * wl[0] + k.gi[sidx(i, 1)] * wl[1] + k.gi[sidx(i, 2)] * wl[2];
+    }
     const S w2 = wl[0] * w[0] + wl[1] * w[1] + wl[2] * w[2];
     if (!(val(w2) < 1.0)) return false;
     const S omw = 1.0 - w2;
@@ -730,7 +740,8 @@ enum : int { ST_OK = 0, ST_WARN = 1, ST_NOCONV = -3, ST_UNPHYS = -4 };
 // hand, the v columns by one 3-direction dual pass): JAC_OK, or JAC_UNPHYS (x
 // outside the physical domain), or JAC_SINGULAR
 enum { JAC_OK = 0, JAC_UNPHYS = 1, JAC_SINGULAR = 2 };
-__device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, double Ji[4][4], double* r) {
+template <bool DG>
+__device__ __forceinline__ int rec_jacobian(const RecInT<double, DG>& k, const double* x, double Ji[4][4], double* r) {
     double J[4][4];
     double c0[4];
     if (!rec_residual<double>(k, x, r, (double*)nullptr, c0)) return JAC_UNPHYS;
@@ -755,7 +766,8 @@ __device__ __forceinline__ int rec_jacobian(const RecIn& k, const double* x, dou
 // fast (chord steps) and refreshed otherwise; backtracking keeps the state
 // physical and the residual decreasing.  x in/out: guess -> (p, v^i);
 // E out: densitised E at the root.
-__device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, int maxit, int* iters) {
+template <bool DG>
+__device__ int recover_stiff(const RecInT<double, DG>& k, double* x, double* E, double tol, int maxit, int* iters) {
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
     double r[4], Ji[4][4];
     int it = 0, restart = 0;
@@ -819,16 +831,25 @@ __device__ int recover_stiff(const RecIn& k, double* x, double* E, double tol, i
 // Plain recovery with E fixed (Sec. III.B): the velocity follows from p
 // alone, and p is updated by the Newton step with f' = v^2 c_s^2 - 1,
 // c_s^2 = Gamma (Gamma-1) eps / (1 + Gamma eps).  x in/out = (p, v).
-__device__ int recover_plain(const RecIn& k, const double* Ec, double* x, double tol, int maxit, int* iters) {
+template <bool DG>
+__device__ int recover_plain(const RecInT<double, DG>& k, const double* Ec, double* x, double tol, int maxit,
+                             int* iters) {
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
     double El[3];
-    lower(k.g, Ec, El);
+    if constexpr (DG) {
+        for (int i = 0; i < 3; ++i) El[i] = k.g[sidx(i, i)] * Ec[i];
+    } else {
+        lower(k.g, Ec, El);
+    }
     const double em = (dot3(El, Ec) + dot3(k.Bl, k.Bc) * k.sg) * (0.5 * k.isg);
     const double base = k.tau + k.D - em;
     double sm[3] = {k.S[0] - (Ec[1] * k.Bc[2] - Ec[2] * k.Bc[1]), k.S[1] - (Ec[2] * k.Bc[0] - Ec[0] * k.Bc[2]),
                     k.S[2] - (Ec[0] * k.Bc[1] - Ec[1] * k.Bc[0])};
     double smu[3];
-    for (int i = 0; i < 3; ++i) smu[i] = k.gi[sidx(i, 0)] * sm[0] + k.gi[sidx(i, 1)] * sm[1] + k.gi[sidx(i, 2)] * sm[2];
+    for (int i = 0; i < 3; ++i) {
+        if constexpr (DG) smu[i] = k.gi[sidx(i, i)] * sm[i];
+        else smu[i] = k.gi[sidx(i, 0)] * sm[0] + k.gi[sidx(i, 1)] * sm[1] + k.gi[sidx(i, 2)] * sm[2];
+    }
     const double s2 = dot3(sm, smu);
     double p = x[0];
     double last_rel = 1e300;
