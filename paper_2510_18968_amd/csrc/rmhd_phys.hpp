@@ -820,6 +820,13 @@ __device__ int recover_stiff(const RecInT<double, DG>& k, double* x, double* E, 
         last_rel = dp / x[0];
         if (dp <= tol * x[0] && dv <= tol) { *iters = it; return ST_OK; }
         const double step = fmax(last_rel, dv);
+        // a full step that contracted by q < 1/4 leaves an error of at most
+        // about q step / (1 - q): once that is below tol / 100 the next step
+        // would only confirm convergence, so stop here
+        if (t == 1.0 && prev_step < 1e300 && step <= 0.25 * prev_step && step * step <= 0.0075 * tol * prev_step) {
+            *iters = it;
+            return ST_OK;
+        }
         if (t < 1.0 || step > 0.25 * prev_step) need = true;
         else fresh = false;
         prev_step = step;
