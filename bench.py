@@ -47,8 +47,8 @@ PEAK_FP64_VECTOR_TFLOPS = 78.6
 STAGE_FLOOR_BYTES = 464
 
 # Per interior cell and launch of each kernel class on the 256^3 curved WENO5
-# workload (zero shift and extrinsic curvature, so the metric read is alpha and
-# gamma_ij, 7 words):
+# workload (zero shift and extrinsic curvature and a diagonal 3-metric, so the
+# metric read is alpha and the diagonal of gamma_ij, 4 words):
 #  * BYTES_PER_CELL: each word the kernel as designed reads or writes, once
 #    (this includes the 14-field flux-divergence accumulator between the
 #    launches, which the stage floor above does not);
@@ -61,21 +61,21 @@ STAGE_FLOOR_BYTES = 464
 # (profiles/counters_curved256_weno5.md); they are re-measured when a kernel
 # changes.
 BYTES_PER_CELL = {
-    # P 14 + sigma 1 + metric 7 read, rhs 14 written
-    "flux_x": 8 * (14 + 1 + 7 + 14),
+    # P 14 + sigma 1 + metric 4 read, rhs 14 written
+    "flux_x": 8 * (14 + 1 + 4 + 14),
     # as x, plus the read half of the rhs read-modify-write
-    "flux_y": 8 * (14 + 1 + 7 + 14 + 14),
-    "flux_z": 8 * (14 + 1 + 7 + 14 + 14),
+    "flux_y": 8 * (14 + 1 + 4 + 14 + 14),
+    "flux_z": 8 * (14 + 1 + 4 + 14 + 14),
     # P(1) 7 (p, v and the cleaning fields: the guess and, without K, all the
-    # local sources read), U^n 14, rhs 14, R1 3, sigma 1, metric 7 read;
+    # local sources read), U^n 14, rhs 14, R1 3, sigma 1, metric 4 read;
     # U(2) 14, P(2) 14, R2 3 written
-    "update_stage2": 8 * (7 + 14 + 14 + 3 + 1 + 7 + 14 + 14 + 3),
+    "update_stage2": 8 * (7 + 14 + 14 + 3 + 1 + 4 + 14 + 14 + 3),
     # ghost layers only
     "ghost_fill": 0,
 }
-FLOPS_PER_CELL = {"flux_x": 2920.5, "flux_y": 2687.0, "flux_z": 2689.0, "update_stage2": 2091.1}
-TRAFFIC_BYTES_PER_CELL = {"flux_x": 201.8 + 120.0, "flux_y": 292.9 + 112.0, "flux_z": 292.9 + 112.0,
-                          "update_stage2": 368.3 + 248.0}
+FLOPS_PER_CELL = {"flux_x": 2576.1, "flux_y": 2339.6, "flux_z": 2341.6, "update_stage2": 1693.4}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 178.1 + 120.1, "flux_y": 268.3 + 112.0, "flux_z": 268.3 + 112.0,
+                          "update_stage2": 344.3 + 248.0}
 
 
 def parse():
