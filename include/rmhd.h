@@ -188,6 +188,18 @@ int rmhd_imex_stage(rmhd_ctx* ctx, int stage, double dt, const double* sigma, co
  * buffers live in the workspace. */
 int rmhd_step(rmhd_ctx* ctx, double dt, const double* sigma, double* U, double* P);
 
+/* nsteps IMEX-SSP2(2,2,2) steps in place (table imex, eq. IMEX3), the results
+ * of nsteps calls of rmhd_step up to rounding (the fused kernel's arithmetic
+ * may be contracted into FMAs differently): stage 1 of every step after the first
+ * is the pointwise solve of eq. 3D_NR on U^{n+1} guessed from P^{n+1} (Sec.
+ * III.B), which the final update of the step before runs in its own kernel on
+ * the cell it has just recovered.  This saves one pass over U, P, sigma and
+ * the metric and one launch per step.  nsteps = 0 does nothing; nsteps < 0,
+ * dt <= 0 or a null argument (sigma may be NULL with a conductivity model) is
+ * RMHD_EINVAL with nothing launched.  Failed cells of every stage count in
+ * rmhd_failures; the recovery histogram sees the same stages as rmhd_step. */
+int rmhd_steps(rmhd_ctx* ctx, double dt, const double* sigma, double* U, double* P, int nsteps);
+
 /* Bytes of caller-provided device scratch rmhd_step_adjoint needs (79 padded
  * fields: adjoint buffers and per-face sensitivities). */
 size_t rmhd_adjoint_workspace_bytes(const rmhd_grid_desc* desc);

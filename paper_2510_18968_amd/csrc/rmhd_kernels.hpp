@@ -1023,7 +1023,8 @@ struct StageIn {
 
 // Inputs of a stage kernel as a list of streams (array, field), each one
 // [Np] row of doubles.  STAGE 1: U^n, the (p, v) guess, sigma, metric;
-// 2: + P(1), rhs, R1, K; 3: P(2), U^n, U(2), rhs, R1, R2, metric, K.
+// 2: + P(1), rhs, R1, K; 3: P(2), U^n, U(2), rhs, R1, R2, metric, K;
+// 4 (the final update followed by the next step's stage 1): 3 + sigma.
 // Without K the local sources need only v and the cleaning fields of P_s,
 // and the guess p and v: the other seven primitives are not loaded.
 enum : int { SA_UN, SA_US, SA_PS, SA_R1, SA_R2, SA_RHS, SA_SIG, SA_ALP, SA_GAM, SA_K };
@@ -1047,12 +1048,11 @@ template <int STAGE, bool CURVED, bool HASK, bool DG> __host__ __device__ conste
         for (int f = 0; f < NF; ++f) add(SA_RHS, f);
         for (int i = 0; i < 3; ++i) add(SA_R1, i);
     }
-    if (STAGE == 3) {
+    if (STAGE >= 3) {
         for (int f = 0; f < NF; ++f) add(SA_US, f);
         for (int i = 0; i < 3; ++i) add(SA_R2, i);
-    } else {
-        add(SA_SIG, 0);
     }
+    if (STAGE != 3) add(SA_SIG, 0);
     if (CURVED) {
         add(SA_ALP, 0);
         for (int a = 0; a < 6; ++a)
@@ -1140,13 +1140,12 @@ __device__ __forceinline__ void stage_read(const Params& p, const Chunk& c, cons
         for (int f = 0; f < NF; ++f) in.rh[f] = rd(SA_RHS, f);
         for (int i = 0; i < 3; ++i) in.R1[i] = rd(SA_R1, i);
     }
-    if (STAGE == 3) {
+    if (STAGE >= 3) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) in.Us[f] = rd(SA_US, f);
         for (int i = 0; i < 3; ++i) in.R2[i] = rd(SA_R2, i);
-    } else {
-        in.sg = rd(SA_SIG, 0);
     }
+    if (STAGE != 3) in.sg = rd(SA_SIG, 0);
     if (CURVED) {
         in.a = rd(SA_ALP, 0);
         for (int a = 0; a < 6; ++a) in.g[a] = rd(SA_GAM, a);
@@ -1206,11 +1205,16 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
 }
 
 // stage 2 (STAGE = 2) and the final update (STAGE = 3), after the flux
-// divergence (with the metric-derivative sources) of P_s is in rhs
+// divergence (with the metric-derivative sources) of P_s is in rhs.
+// STAGE = 4: the final update, then the next step's stage 1 on U^{n+1}
+// guessed from P^{n+1} into P1o and Ro (to rounding, the results of stage1_cell on the
+// stored U^{n+1} and P^{n+1}: the same recovery on the same inputs, which the
+// plain recovery's setup already holds), tallied in tal1.
 template <int STAGE, bool CURVED, bool HASK, bool DG>
 __device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
                                             double* __restrict__ Po, double* __restrict__ Ro,
-                                            int* __restrict__ status, long st_stride, StageTally& tal) {
+                                            double* __restrict__ P1o, int* __restrict__ status, long st_stride,
+                                            StageTally& tal, StageTally& tal1) {
     const long Np = p.Np, o = in.o;
     Geo<double, DG> m;
     stage_geo<CURVED>(in, m);
@@ -1239,7 +1243,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
                 for (int i = 0; i < 3; ++i) Y[I_E + i] += 0.5 * dt * (2.0 * g * in.R1[i] + (1.0 - g) * in.R2[i]);
             }
         }
-        if (STAGE == 3 && p.rho_atmo > 0.0 && Y[I_D] < ATMO_FACTOR * m.sg * p.rho_atmo) {
+        if (STAGE >= 3 && p.rho_atmo > 0.0 && Y[I_D] < ATMO_FACTOR * m.sg * p.rho_atmo) {
             // artificial atmosphere (Sec. IV.E): the hydro part of the state
             // rho_atmo, v = 0, p_atmo with the cell's own fields
             double Pa[NF], Ua[NF];
@@ -1254,7 +1258,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
         YD = Y[I_D];
         __builtin_amdgcn_sched_barrier(0);
         for (int f = 0; f < NF; ++f)
-            if (STAGE == 3 || f < I_E || f >= I_E + 3) Uo[f * Np + o] = Y[f];
+            if (STAGE >= 3 || f < I_E || f >= I_E + 3) Uo[f * Np + o] = Y[f];
         rec_setup(p, m, Y, k);
         for (int i = 0; i < 3; ++i) cl[i] = Y[I_PHI + i];
         if (STAGE == 2)
@@ -1274,8 +1278,7 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     }
     __builtin_amdgcn_sched_barrier(0);
     tally_cell(tal, p.hist != nullptr, in.ok, st, it);
-    (void)YD;
-    if (STAGE == 3 && atmo && st >= 0) {
+    if (STAGE >= 3 && atmo && st >= 0) {
         st = 2;                                           // flagged: atmosphere
         if (in.ok) atomicAdd(&tal.atmo, 1u);
     }
@@ -1292,36 +1295,63 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
             Ro[i * Np + o] = (E[i] - k.Es[i]) / (g * dt);
         }
     }
-    status[st_stride * o] = st;
+    if (STAGE != 4) status[st_stride * o] = st;
+    if (STAGE == 4) {
+        // stage 1 of the next step: E(1) = E^{n+1} + gamma dt R_E(U(1)); a
+        // failed cell keeps the guess and E^{n+1}, as in stage1_cell
+        __builtin_amdgcn_sched_barrier(0);
+        const double gdt = g * dt;
+        k.cfac = gdt * m.alp * (p.sig_model ? sigma_of_D(p, YD) : in.sg);
+        const double xg[4] = {x[0], x[1], x[2], x[3]};
+        double E1[3] = {k.Es[0], k.Es[1], k.Es[2]};
+        int it1, st1;
+        if (k.cfac != 0.0) st1 = recover_stiff(k, x, E1, p.tol, p.maxit, &it1);
+        else st1 = recover_plain(k, E1, x, p.tol, p.maxit, &it1);
+        __builtin_amdgcn_sched_barrier(0);
+        tally_cell(tal1, p.hist != nullptr, in.ok, st1, it1);
+        if (st1 < 0)
+            for (int i = 0; i < 4; ++i) x[i] = xg[i];
+        if (st1 < 0)
+            for (int i = 0; i < 3; ++i) E1[i] = k.Es[i];
+        write_prims_k(p, o, m, k, cl, x, E1, P1o);
+        for (int i = 0; i < 3; ++i) Ro[i * Np + o] = (E1[i] - k.Es[i]) / gdt;
+        status[st_stride * o] = st1;
+    }
 }
 
 // stores of one chunk per lane: every one is taken on every path
-template <int STAGE> constexpr int stage_stores() { return STAGE == 1 ? 18 : (STAGE == 2 ? 32 : 29); }
+template <int STAGE> constexpr int stage_stores() {
+    return STAGE == 1 ? 18 : (STAGE == 2 ? 32 : (STAGE == 3 ? 29 : 28 + 18));
+}
 
 // STAGE 1: stage1_cell (Us, R2, rhs unused; Ps = the guess, Uo = U1, Ro = R1)
-// STAGE 2, 3: update_cell.  HASK: nonzero extrinsic curvature.  status is
-// written at status[st_stride * o] (st_stride 0: one dummy word).
+// STAGE 2, 3: update_cell.  STAGE 4: update_cell's final update with the next
+// step's stage 1 (Ro = R1 of the next step, which may be the R1 read here:
+// each cell's inputs are in LDS before its stores; P1o = its P(1)).  HASK:
+// nonzero extrinsic curvature.  status is written at status[st_stride * o]
+// (st_stride 0: one dummy word; STAGE 4 writes only its stage 1's status).
 // Persistent, one wave per block (and per SIMD: the recovery's registers
 // allow no more), walking chunks q, q + W, ...  The next chunk's inputs are
 // loaded into the wave's LDS buffer while the current chunk (read from it
 // into registers first) is computed and stored; the wait for them leaves the
 // current chunk's stores in flight (stage 1 stores 18 or 32 per chunk, so
-// waiting for 18 is safe in both cases).
+// waiting for 18 is safe in both cases).  Uo may be Un (the final update in
+// place) and Ro may be R1 (STAGE 4), so those four are not restrict.
 template <int STAGE, bool CURVED, bool HASK, bool DG>
 __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const double* __restrict__ sig,
-                                              const double* __restrict__ Un, const double* __restrict__ Us,
-                                              const double* __restrict__ Ps, const double* __restrict__ R1,
+                                              const double* Un, const double* __restrict__ Us,
+                                              const double* __restrict__ Ps, const double* R1,
                                               const double* __restrict__ R2, const double* __restrict__ rhs,
-                                              double* __restrict__ Uo, double* __restrict__ Po,
-                                              double* __restrict__ Ro, int* __restrict__ status, long st_stride,
-                                              unsigned long long* nfail) {
+                                              double* Uo, double* __restrict__ Po,
+                                              double* Ro, double* __restrict__ P1o, int* __restrict__ status,
+                                              long st_stride, unsigned long long* nfail) {
     constexpr int NS = stage_streams<STAGE, CURVED, HASK, DG>().n;
     static_assert(NS <= 80 && NS % 2 == 0, "stream list");
     __shared__ double buf[NS * 64];
-    __shared__ StageTally tal;
+    __shared__ StageTally tal, tal1;
     const int lane = threadIdx.x;
-    if (lane < 32) tal.hist[lane] = 0u;
-    if (lane == 0) tal.fail = tal.atmo = 0u;
+    if (lane < 32) tal.hist[lane] = tal1.hist[lane] = 0u;
+    if (lane == 0) tal.fail = tal.atmo = tal1.fail = tal1.atmo = 0u;
     const int nsx = (p.n[0] + 63) / 64;
     const long nchunk = (long)nsx * p.n[1] * p.n[2];
     const long W = gridDim.x;
@@ -1341,7 +1371,7 @@ __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const d
             // unconditional (the last pass reloads its own chunk)
             stage_issue<STAGE, CURVED, HASK, DG>(p, A, cn, buf, lane);
             if (STAGE == 1) stage1_cell<CURVED, DG>(p, dt, in, Po, Ro, Uo, status, st_stride, tal);
-            else update_cell<STAGE, CURVED, HASK, DG>(p, dt, in, Uo, Po, Ro, status, st_stride, tal);
+            else update_cell<STAGE, CURVED, HASK, DG>(p, dt, in, Uo, Po, Ro, P1o, status, st_stride, tal, tal1);
             // the loads above were followed by this chunk's stores only
             wait_vm<stage_stores<STAGE>()>();
             if (qn >= nchunk) break;
@@ -1353,10 +1383,12 @@ __global__ __launch_bounds__(64) void k_stage(const Params p, double dt, const d
     __syncthreads();
     // histogram bins: stage 1 0..31, stage 2 32..63, final 64..95
     if (p.hist && lane < 32 && tal.hist[lane])
-        atomicAdd(p.hist + 32 * (STAGE - 1) + lane, (unsigned long long)tal.hist[lane]);
-    if (lane == 0 && tal.fail) atomicAdd(nfail, (unsigned long long)tal.fail);
+        atomicAdd(p.hist + 32 * (STAGE == 4 ? 2 : STAGE - 1) + lane, (unsigned long long)tal.hist[lane]);
+    if (STAGE == 4 && p.hist && lane < 32 && tal1.hist[lane])
+        atomicAdd(p.hist + lane, (unsigned long long)tal1.hist[lane]);
+    if (lane == 0 && tal.fail + tal1.fail) atomicAdd(nfail, (unsigned long long)(tal.fail + tal1.fail));
     // nfail[4]: cells set to the atmosphere (the context's counter block)
-    if (STAGE == 3 && lane == 0 && tal.atmo) atomicAdd(nfail + 4, (unsigned long long)tal.atmo);
+    if (STAGE >= 3 && lane == 0 && tal.atmo) atomicAdd(nfail + 4, (unsigned long long)tal.atmo);
 }
 
 // conductivity model at the interior cells from the primitives P (D =

@@ -24,7 +24,7 @@ SYMBOLS = ("rmhd_workspace_bytes", "rmhd_padded_extent", "rmhd_init_grid", "rmhd
            "rmhd_imex_stage", "rmhd_step", "rmhd_max_signal_speed", "rmhd_failures", "rmhd_destroy",
            "rmhd_last_error", "rmhd_timing", "rmhd_timing_read", "rmhd_adjoint_workspace_bytes",
            "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read", "rmhd_set_stream",
-           "rmhd_step_adjoint_static", "rmhd_atmosphere_cells")
+           "rmhd_step_adjoint_static", "rmhd_atmosphere_cells", "rmhd_steps")
 HIST_BINS = 32
 TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
 
@@ -70,6 +70,7 @@ def lib() -> C.CDLL:
             "rmhd_con2prim": (C.c_int, [vp, vp, vp, vp]),
             "rmhd_imex_stage": (C.c_int, [vp, C.c_int, C.c_double, vp, C.POINTER(StageBufs)]),
             "rmhd_step": (C.c_int, [vp, C.c_double, vp, vp, vp]),
+            "rmhd_steps": (C.c_int, [vp, C.c_double, vp, vp, vp, C.c_int]),
             "rmhd_max_signal_speed": (C.c_int, [vp, C.POINTER(C.c_double)]),
             "rmhd_failures": (C.c_int, [vp, C.POINTER(C.c_int64)]),
             "rmhd_atmosphere_cells": (C.c_int, [vp, C.POINTER(C.c_int64)]),
@@ -253,6 +254,11 @@ class Grid:
     def step(self, dt, sigma, U, P):
         _check(lib().rmhd_step(self._ctx, float(dt), self._ptr(sigma), self._ptr(U, 14), self._ptr(P, 14)),
                "rmhd_step")
+
+    def steps(self, dt, sigma, U, P, n):
+        """n steps in place; each final update runs the next step's stage 1"""
+        _check(lib().rmhd_steps(self._ctx, float(dt), self._ptr(sigma), self._ptr(U, 14), self._ptr(P, 14), int(n)),
+               "rmhd_steps")
 
     def max_signal_speed(self) -> float:
         v = C.c_double()

@@ -1,11 +1,11 @@
-// Instantiates every stage kernel, the FP64 x-flux kernels and y/z window
-// kernels (general and diagonal metric) so that their gfx950 assembly can be
-// checked (tests/test_stage_waits.py); never linked into the library.
+// Instantiates every stage kernel (the fused final update + stage 1 too),
+// the FP64 x-flux kernels and y/z window kernels (general and diagonal
+// metric) so that their gfx950 assembly can be checked (tests/test_stage_waits.py); never linked into the library.
 #include <hip/hip_runtime.h>
 #include "rmhd_kernels.hpp"
 using namespace rmhd;
 template <int S, bool C, bool K, bool DG> void inst(const Params& p, double* a, unsigned long long* c, int* s) {
-    k_stage<S, C, K, DG><<<1, 64>>>(p, 0.1, a, a, a, a, a, a, a, a, a, a, s, 1L, c);
+    k_stage<S, C, K, DG><<<1, 64>>>(p, 0.1, a, a, a, a, a, a, a, a, a, a, a, s, 1L, c);
 }
 template <int RC, bool C, bool DG> void inst_x(const Params& p, double* a) {
     k_flux_p<0, RC, C, double, false, DG><<<8, 256>>>(p, a, a, a, 1, 1L);
@@ -30,5 +30,5 @@ void all(const Params& p, double* a, unsigned long long* c, int* s) {
     inst_x<0, false, false>(p, a); inst_x<1, false, false>(p, a); inst_x<2, false, false>(p, a);
     inst_x<0, true, false>(p, a); inst_x<1, true, false>(p, a); inst_x<2, true, false>(p, a);
     inst_x<0, true, true>(p, a); inst_x<1, true, true>(p, a); inst_x<2, true, true>(p, a);
-    stages<1>(p, a, c, s); stages<2>(p, a, c, s); stages<3>(p, a, c, s);
+    stages<1>(p, a, c, s); stages<2>(p, a, c, s); stages<3>(p, a, c, s); stages<4>(p, a, c, s);
 }

@@ -34,7 +34,7 @@ def asm(tmp_path_factory):
     return kernels(out.read_text())
 
 
-@pytest.mark.parametrize("kind,count,load", [("k_stage", 15, "global_load_lds_dwordx4"),
+@pytest.mark.parametrize("kind,count,load", [("k_stage", 20, "global_load_lds_dwordx4"),
                                              ("k_flux_p", 9, "global_load_dwordx2")])
 def test_kernel_waits_cover_their_loads(asm, kind, count, load):
     ks = {k: v for k, v in asm.items() if kind in k}
