@@ -128,7 +128,9 @@ enum rmhd_sigma_model { RMHD_SIGMA_FIELD = 0, RMHD_SIGMA_POWER = 1, RMHD_SIGMA_D
  *                              out U_out = U(2), P_out = P(2), R_out = R2
  *   stage 3 (final update):    in U_n, U_s = U(2), P_in = P(2), R1, R2
  *                              out U_out = U^{n+1}, P_out = P^{n+1}
- * Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  For stage 3,
+ * Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  Stage 2 may
+ * also overwrite the x ghost cell next to the interior of each row of U_out,
+ * P_out, R_out and status (when n_x is not a multiple of 64).  For stage 3,
  * U_out may alias U_n and P_out may alias nothing else.  status is optional
  * ([Np] int32, interior cells written).  A cell whose recovery fails (status
  * < 0, counted by rmhd_failures) gets the primitives of its stage state at
@@ -278,12 +280,14 @@ int rmhd_recovery_stats_read(rmhd_ctx* ctx, int64_t* bins_out);
  * the library brackets every launch with HIP events on the context's stream,
  * grouped by kernel class: 0 ghost fill, 1 x fluxes, 2 y fluxes, 3 z fluxes,
  * 4 stage-2 update + stiff recovery, 5 final update + recovery, 6 stage 1,
- * 7 other pointwise kernels.  rmhd_timing_read synchronises the stream,
+ * 7 other pointwise kernels, 8 z fluxes with the stage-2 update of each
+ * finished row (stage 2 on 3D grids without extrinsic curvature, which then
+ * has no class-4 launch).  rmhd_timing_read synchronises the stream,
  * writes the summed milliseconds and launch counts of each class since the
  * last read (arrays of RMHD_TIMING_CLASSES entries) and resets them.  If an
  * event could not be created or recorded since the last read, it resets the
  * counts, writes nothing and returns RMHD_EHIP (the launches themselves ran). */
-#define RMHD_TIMING_CLASSES 8
+#define RMHD_TIMING_CLASSES 9
 int rmhd_timing(rmhd_ctx* ctx, int enable);
 int rmhd_timing_read(rmhd_ctx* ctx, double* ms_out, int64_t* launches_out);
 

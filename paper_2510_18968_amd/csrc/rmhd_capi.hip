@@ -151,7 +151,7 @@ size_t ws_layout(const rmhd_grid_desc* d, size_t off[8]) {
 
 long ncells(const Params& p) { return (long)p.n[0] * p.n[1] * p.n[2]; }
 
-enum { T_GHOST = 0, T_FX = 1, T_FY = 2, T_FZ = 3, T_UPD2 = 4, T_UPD3 = 5, T_STAGE1 = 6, T_OTHER = 7 };
+enum { T_GHOST = 0, T_FX = 1, T_FY = 2, T_FZ = 3, T_UPD2 = 4, T_UPD3 = 5, T_STAGE1 = 6, T_OTHER = 7, T_FZU = 8 };
 
 // brackets one launch with events when timing is on
 struct Timed {
@@ -215,7 +215,8 @@ template <int D, int RECON, bool CURVED, class R, bool ACC, bool DG> void flux_t
     }
 }
 
-template <int D, int RECON, bool CURVED, class R, bool DG> void flux_w(rmhd_ctx* c, const double* P, const double* sig) {
+template <int D, int RECON, bool CURVED, class R, bool DG, bool FUSE = false>
+void flux_w(rmhd_ctx* c, const double* P, const double* sig, const FuseArgs& fz = FuseArgs{}) {
     const Params& p = c->p;
     constexpr int E = (D == 1) ? 2 : 1;
     // segments as long as possible (each re-loads 3 halo rows at both ends
@@ -229,13 +230,18 @@ template <int D, int RECON, bool CURVED, class R, bool DG> void flux_w(rmhd_ctx*
     const int nseg = (p.n[D] + seglen - 1) / seglen;
     const long waves = (long)nxb * p.n[E] * nseg;
     const long blocks = (waves + 7) / 8 * 8;          // one wave per block; multiple of 8 for the XCD renumbering
-    if (CURVED && p.bet)
-        k_flux_w<D, RECON, CURVED, R, true, DG><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+    // (the fused form runs without a shift only)
+    if (!FUSE && CURVED && p.bet)
+        k_flux_w<D, RECON, CURVED, R, !FUSE, DG, FUSE><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb,
+                                                                                      nseg, fz);
     else
-        k_flux_w<D, RECON, CURVED, R, false, DG><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb, nseg);
+        k_flux_w<D, RECON, CURVED, R, false, DG, FUSE><<<blocks, 64, 0, c->stream>>>(p, P, sig, c->rhs, seglen, nxb,
+                                                                                      nseg, fz);
 }
 
-template <int RECON, bool CURVED, class R, bool DG> int flux_div_t(rmhd_ctx* c, const double* P, const double* sig) {
+// fz: the z sweep also runs stage 2 on the rows it finishes (z active)
+template <int RECON, bool CURVED, class R, bool DG>
+int flux_div_t(rmhd_ctx* c, const double* P, const double* sig, const FuseArgs* fz) {
     const Params& p = c->p;
     {
         Timed t(c, T_FX);
@@ -248,35 +254,44 @@ template <int RECON, bool CURVED, class R, bool DG> int flux_div_t(rmhd_ctx* c, 
         LAUNCH_CHECK();
     }
     if (is_active(p, 2)) {
-        Timed t(c, T_FZ);
-        flux_w<2, RECON, CURVED, R, DG>(c, P, sig);
+        Timed t(c, fz ? T_FZU : T_FZ);
+        // the fused instances that stage 2 launches (FP64, MC2 or minmod,
+        // flat or diagonal metric)
+        constexpr bool FUSABLE = std::is_same<R, double>::value && RECON != REC_WENO5 && (!CURVED || DG);
+        if constexpr (FUSABLE) {
+            if (fz) flux_w<2, RECON, CURVED, R, DG, true>(c, P, sig, *fz);
+            else flux_w<2, RECON, CURVED, R, DG>(c, P, sig);
+        } else {
+            if (fz) return fail(RMHD_EINVAL, "no fused z sweep for this configuration");
+            flux_w<2, RECON, CURVED, R, DG>(c, P, sig);
+        }
         LAUNCH_CHECK();
     }
     return RMHD_OK;
 }
 
-template <class R> int flux_div_r(rmhd_ctx* c, const double* P, const double* sig) {
+template <class R> int flux_div_r(rmhd_ctx* c, const double* P, const double* sig, const FuseArgs* fz) {
     const int r = c->desc.recon;
     if (c->curved && c->diag) {
-        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R, true>(c, P, sig);
-        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R, true>(c, P, sig);
-        return flux_div_t<REC_WENO5, true, R, true>(c, P, sig);
+        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R, true>(c, P, sig, fz);
+        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R, true>(c, P, sig, fz);
+        return flux_div_t<REC_WENO5, true, R, true>(c, P, sig, fz);
     }
     if (c->curved) {
-        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R, false>(c, P, sig);
-        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R, false>(c, P, sig);
-        return flux_div_t<REC_WENO5, true, R, false>(c, P, sig);
+        if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, true, R, false>(c, P, sig, fz);
+        if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, true, R, false>(c, P, sig, fz);
+        return flux_div_t<REC_WENO5, true, R, false>(c, P, sig, fz);
     }
-    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false, R, false>(c, P, sig);
-    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false, R, false>(c, P, sig);
-    return flux_div_t<REC_WENO5, false, R, false>(c, P, sig);
+    if (r == RMHD_RECON_MINMOD) return flux_div_t<REC_MINMOD, false, R, false>(c, P, sig, fz);
+    if (r == RMHD_RECON_MC2) return flux_div_t<REC_MC2, false, R, false>(c, P, sig, fz);
+    return flux_div_t<REC_WENO5, false, R, false>(c, P, sig, fz);
 }
 
 // minus the flux divergence of the (ghost-filled) primitives P into c->rhs;
 // FP32 reconstruction / HLLE / divergence in the mixed-precision form
-int flux_div(rmhd_ctx* c, const double* P, const double* sig) {
-    if (c->desc.precision == RMHD_PREC_MIXED) return flux_div_r<float>(c, P, sig);
-    return flux_div_r<double>(c, P, sig);
+int flux_div(rmhd_ctx* c, const double* P, const double* sig, const FuseArgs* fz = nullptr) {
+    if (c->desc.precision == RMHD_PREC_MIXED) return flux_div_r<float>(c, P, sig, fz);
+    return flux_div_r<double>(c, P, sig, fz);
 }
 
 // persistent stage kernels: one one-wave block per SIMD (4 per CU)
@@ -347,6 +362,20 @@ int stage2(rmhd_ctx* c, double dt, const double* sig, const double* Un, double* 
     if ((r = ghost_fill(c, P1, NF)) != RMHD_OK) return r;
     const double* fs = nullptr;
     if ((r = flux_sigma(c, P1, sig, &fs)) != RMHD_OK) return r;
+    // The z sweep with the update in one kernel measured faster for FP64
+    // MC2 and minmod on flat or diagonal metrics (256^3 blob, MC2: 3.40 ->
+    // 2.86 ms for z sweep + update); with WENO5 (FP64 or mixed) or in the
+    // mixed form the window and the recovery do not share the registers well
+    // and it measured slower, so those keep the separate update.
+    const bool fuse = is_active(c->p, 2) && c->desc.precision == RMHD_PREC_FP64 &&
+                      c->desc.recon != RMHD_RECON_WENO5 && (!c->curved || c->diag) && !c->p.bet && !c->p.K &&
+                      c->desc.sigma_model == RMHD_SIGMA_FIELD;
+    if (fuse) {
+        // the z sweep runs the update on each row it finishes
+        int32_t* dummy = reinterpret_cast<int32_t*>(c->counters + 3);
+        FuseArgs fz{Un, R1, U2, P2, R2, st ? st : dummy, st ? 1L : 0L, dt, c->counters, dummy};
+        return flux_div(c, P1, fs, &fz);
+    }
     if ((r = flux_div(c, P1, fs)) != RMHD_OK) return r;
     // (with a model the stage kernel takes sigma from D of its stage state;
     // the sigma stream it loads is then a placeholder)
@@ -608,6 +637,7 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
         p.bc[d] = desc->bc[d];
         p.dx[d] = desc->dx[d];
         p.idx[d] = ((desc->active_mask >> d) & 1) ? 1.0 / desc->dx[d] : 0.0;
+        p.cdiff[d] = p.idx[d] / 12.0;
     }
     p.st[0] = 1;
     p.st[1] = p.np[0];
@@ -620,6 +650,7 @@ int rmhd_init_grid(const rmhd_grid_desc* desc, void* workspace, size_t ws_bytes,
     p.G = desc->gamma_ad;
     p.kappa = desc->kappa;
     p.tol = desc->c2p_tol;
+    p.tolq = 0.0075 * p.tol;
     p.sig_model = desc->sigma_model;
     p.sig0 = desc->sigma0;
     p.sig_exp = desc->sigma_exp;

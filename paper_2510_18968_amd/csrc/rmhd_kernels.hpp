@@ -24,6 +24,10 @@ struct Params {
     int n[3], g[3], np[3], ng, active, bc[3], maxit, speed_mode;
     long st[3], Np;
     double dx[3], idx[3], G, kappa, tol;
+    double cdiff[3];            // idx / 12: the 4th-order centred difference's factor
+    double tolq;                // 0.0075 tol: the stiff recovery's early stop (kernel arguments
+                                // live in scalar registers; a product formed on the device
+                                // would hold two vector registers in every kernel that inlines it)
     // metric (nullptr alp/gam: flat), beta/K may be nullptr
     const double* alp;
     const double* bet;
@@ -419,6 +423,39 @@ __global__ __launch_bounds__(256) void k_flux_p(const Params p, const double* __
     }
 }
 
+// gamma of table imex
+__host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560; }
+
+// per-block tallies of the stage kernels in LDS (recovery iteration
+// histogram, failed cells), added to the global counters once per block at
+// the end: inside the chunk loop no global atomic sits between the next
+// chunk's loads and the wait for them
+struct StageTally {
+    unsigned int hist[32];
+    unsigned int fail, atmo;
+};
+__device__ __forceinline__ void tally_cell(StageTally& t, bool hist, bool counted, int st, int it) {
+    if (!counted) return;
+    if (hist) atomicAdd(&t.hist[it < 0 ? 0 : (it > 31 ? 31 : it)], 1u);
+    if (st < 0) atomicAdd(&t.fail, 1u);
+}
+
+// the inputs of one cell's stage update
+struct StageIn {
+    long o;
+    bool ok;
+    double P[NF], Un[NF], rh[NF], Us[NF], R1[3], R2[3], sg, a, g[6], K[6];
+};
+
+// stage 2 / final update of one cell (defined with the stage kernels; the z
+// window runs stage 2 on the rows it finishes).  MODEL = false: sigma is the
+// given field (no conductivity-model code in the caller)
+template <int STAGE, bool CURVED, bool HASK, bool DG, bool MODEL = true>
+__device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
+                                            double* __restrict__ Po, double* __restrict__ Ro,
+                                            double* __restrict__ P1o, int* __restrict__ status, long st_stride,
+                                            StageTally& tal, StageTally& tal1);
+
 // ------------------------------------------- y / z fluxes: rolling window
 // Lanes along x, one wave marches a segment of cells along D.  Every row of P
 // is loaded once, straight from HBM into a ring of the last five rows in LDS
@@ -445,13 +482,37 @@ __device__ __forceinline__ void wait_ring() {
 // packed index of the j-th stored metric component (DG: the diagonal only)
 template <bool DG> __host__ __device__ constexpr int gcomp(int j) { return DG ? (j == 0 ? 0 : (j == 1 ? 3 : 5)) : j; }
 
+// The stage-2 update run by the last window sweep on each row it finishes
+// (FUSE): its inputs besides the ring row and the window's metric and sigma,
+// and its outputs (status: st_stride 0 writes one dummy word)
+struct FuseArgs {
+    const double* Un;
+    const double* R1;
+    double* U2;
+    double* P2;
+    double* R2;
+    int* status;
+    long st_stride;
+    double dt;
+    unsigned long long* nfail;
+    int* dummy;              // a word nothing reads
+};
+
 // SHIFT: the metric has a shift (beta rows in the window); without one the
 // window holds alpha, gamma_ij and sigma only.  DG: a diagonal metric, whose
-// window and staging row hold the three diagonal entries of gamma_ij
-template <int D, int RECON, bool CURVED, class R, bool SHIFT, bool DG>
+// window and staging row hold the three diagonal entries of gamma_ij.  FUSE
+// (D = 2, no extrinsic curvature, a sigma field): instead of storing rhs row c - 1, the
+// step runs stage 2 on its cells (update_cell on U^n and R1 loaded for the
+// row, P(1) from the ring, metric and sigma from the window), so the 14-word
+// rhs, P(1), metric and sigma of the stage update make no HBM round trip.
+// A step with no finished row (the first of a segment) sends its 32 stores
+// to an x ghost cell of rhs, which nothing reads; lanes past x's end write
+// the x ghost cell next to the interior of U2, P2, R2 (and status).
+template <int D, int RECON, bool CURVED, class R, bool SHIFT, bool DG, bool FUSE = false>
 __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __restrict__ P,
                                                const double* __restrict__ sig, double* __restrict__ rhs,
-                                               int seglen, int nxb, int nseg) {
+                                               int seglen, int nxb, int nseg, const FuseArgs fz = FuseArgs{}) {
+    static_assert(!FUSE || D == 2, "the stage update follows the last sweep");
     constexpr int E = (D == 1) ? 2 : 1;                 // the other transverse dimension
     constexpr int NG = DG ? 3 : 6;                      // stored gamma_ij components
     // staging streams: sigma; alpha, gamma_ij (curved); beta^i (shift); an even count
@@ -459,11 +520,22 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     // one LDS object for the ring and the staging row: with two objects
     // filled by direct loads the wait-count pass makes every ring read wait
     // for all outstanding memory operations
-    __shared__ double ring[WRING * NF * 64 + NMS * 64];
+    // (FUSE: the stage update's tally at the end of the same object)
+    constexpr int NTAL = FUSE ? (int)((sizeof(StageTally) + 7) / 8) : 0;
+    __shared__ double ring[WRING * NF * 64 + NMS * 64 + NTAL];
     double* const mst = ring + WRING * NF * 64;
+    StageTally& tal = *reinterpret_cast<StageTally*>(ring + WRING * NF * 64 + NMS * 64);
     const int lane = threadIdx.x;
     const long wid = xcd_block();
     if (wid >= (long)nxb * p.n[E] * nseg) return;      // uniform per wave
+    if (FUSE) {
+        if (lane < 32) tal.hist[lane] = 0u;
+        if (lane == 0) tal.fail = tal.atmo = 0u;
+    }
+    // stores of one step: rhs row c - 1, or the stage update's (update_cell)
+    constexpr int NST = FUSE ? 32 : NF;
+    // FUSE: U^n and R1 of row c - 1, loaded with rhs row c - 1
+    constexpr int NUPD = FUSE ? NF + 3 : 0;
     const int xb = (int)(wid % nxb);
     const long r = wid / nxb;
     const int e = (int)(r % p.n[E]);
@@ -479,7 +551,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     const long xpair = min((long)p.g[0] + (long)xb * 64 + 2 * (lane & 31), (long)p.np[0] - 2);
     const int fhalf = lane >> 5;
     const R ih = R(p.idx[D]);
-    const double cd = p.idx[D] / 12.0;
+    const double cd = p.cdiff[D];
     auto slot = [&](int c) { return (c + gD) % WRING; };
     auto ringP = [&](int c, int f) -> double { return ring[(slot(c) * NF + f) * 64 + lane]; };
     auto load_ring = [&](int c) {
@@ -582,6 +654,13 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         double acc[NF];
 #pragma unroll
         for (int f = 0; f < NF; ++f) acc[f] = rhs[f * Np + om];
+        // FUSE: the stage update's inputs of row c - 1 (U^n, R1) with them
+        double un[FUSE ? NF : 1], r1v[FUSE ? 3 : 1];
+        if constexpr (FUSE) {
+#pragma unroll
+            for (int f = 0; f < NF; ++f) un[f] = fz.Un[f * Np + om];
+            for (int a = 0; a < 3; ++a) r1v[a] = fz.R1[a * Np + om];
+        }
         // the sources go to the partial sum: acc is first used at the store,
         // so its loads have the whole step to land
         if (fin && CURVED) {
@@ -594,7 +673,8 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             auto d4 = [&](double a0, double a1, double a3, double a4) { return (a0 - 8.0 * a1 + 8.0 * a3 - a4) * cd; };
             const double da = d4(wa[0], wa[1], wa[3], wa[4]);
             double db[3], dg[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-            for (int a = 0; a < 3; ++a) db[a] = d4(bw(0, a), bw(1, a), bw(3, a), bw(4, a));
+            // (no shift: zero, not 0 * cd, which the compiler must keep)
+            for (int a = 0; a < 3; ++a) db[a] = SHIFT ? d4(bw(0, a), bw(1, a), bw(3, a), bw(4, a)) : 0.0;
             for (int a = 0; a < NG; ++a) dg[gcomp<DG>(a)] = d4(wg[0][a], wg[1][a], wg[3][a], wg[4][a]);
             double Pm[NF], Um[NF];
 #pragma unroll
@@ -622,8 +702,10 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
             Jc = J[D];
         }
         // ring row c + 2 (requested last step) must have landed; issued after
-        // it: rhs row c - 2 written, staging row c + 2 and rhs row c - 1 read
-        wait_vm<NF + NMET + NF>();
+        // it: the last step's stores, staging row c + 2, rhs row c - 1 read
+        // and the update's loads (at most 63 can be left in flight: waiting
+        // for fewer is waiting longer)
+        wait_vm<(NUPD + NST + NMET + NF < 63 ? NUPD + NST + NMET + NF : 63)>();
         // reconstruction of c
         R fm[NF], fp[NF];
 #pragma unroll
@@ -663,15 +745,43 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
                 for (int f = 0; f < NF; ++f) PR[f] = R(ringP(c, f));
             R Fh[NF];
             face_flux<D>(p, m, PLc, PR, R(0.5 * (Jprev + Jc)), Fh);
-            // rhs row c - 1 (read at the top of the step) has landed once no more
-            // than the ring row c + 3 is in flight behind it
+            // rhs row c - 1 (read at the top of the step, with the update's
+            // loads) has landed once no more than the ring row c + 3 is in
+            // flight behind it
             wait_vm<NF / 2>();
             const long os = (fin && valid) ? om : odummy + (long)(c - 1 + gD) * s;
+            if constexpr (FUSE) {
+                StageIn in;
+                in.ok = fin && valid;
+                in.o = os;
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const double fo = double(Fh[f] * ih);
-                rhs[f * Np + os] = acc[f] + (part[f] - fo);
-                part[f] = fo;
+                for (int f = 0; f < NF; ++f) {
+                    const double fo = double(Fh[f] * ih);
+                    in.rh[f] = acc[f] + (part[f] - fo);
+                    part[f] = fo;
+                    in.Un[f] = un[f];
+                    in.P[f] = ringP(c - 1, f);
+                }
+                for (int a = 0; a < 3; ++a) in.R1[a] = r1v[a];
+                in.sg = ws[2];
+                in.a = wa[2];
+                for (int a = 0; a < NG; ++a) in.g[gcomp<DG>(a)] = wg[2][a];
+                // a step without a finished row stores to rhs's x ghost cell of
+                // the row (its status to the dummy word); lanes past x's end
+                // to the outputs' x ghost cell (the bases stay uniform)
+                double* const Uo = fin ? fz.U2 : rhs;
+                double* const Po = fin ? fz.P2 : rhs;
+                double* const Ro = fin ? fz.R2 : rhs;
+                int* const so = fin ? fz.status : fz.dummy;
+                update_cell<2, CURVED, false, DG, false>(p, fz.dt, in, Uo, Po, Ro, nullptr, so,
+                                                         fin ? fz.st_stride : 0L, tal, tal);
+            } else {
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const double fo = double(Fh[f] * ih);
+                    rhs[f * Np + os] = acc[f] + (part[f] - fo);
+                    part[f] = fo;
+                }
             }
         }
 #pragma unroll
@@ -700,6 +810,11 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     }
     // no ring load may be in flight when the wave ends
     wait_ring();
+    if (FUSE) {
+        // stage 2's histogram bins 32..63 and the failure count
+        if (p.hist && lane < 32 && tal.hist[lane]) atomicAdd(p.hist + 32 + lane, (unsigned long long)tal.hist[lane]);
+        if (lane == 0 && tal.fail) atomicAdd(fz.nfail, (unsigned long long)tal.fail);
+    }
 }
 
 // ------------------------------------------------ metric set-up (one-time)
@@ -994,32 +1109,10 @@ __device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m,
 }
 
 // --------------------------------------------------------------- stages
-// gamma of table imex
-__host__ __device__ constexpr double GAM_IMEX() { return 0.29289321881345247560; }
-
-// per-block tallies of the stage kernels in LDS (recovery iteration
-// histogram, failed cells), added to the global counters once per block at
-// the end: inside the chunk loop no global atomic sits between the next
-// chunk's loads and the wait for them
-struct StageTally {
-    unsigned int hist[32];
-    unsigned int fail, atmo;
-};
-__device__ __forceinline__ void tally_cell(StageTally& t, bool hist, bool counted, int st, int it) {
-    if (!counted) return;
-    if (hist) atomicAdd(&t.hist[it < 0 ? 0 : (it > 31 ? 31 : it)], 1u);
-    if (st < 0) atomicAdd(&t.fail, 1u);
-}
-
 // ---------------------------------------------------------- stage kernels
 // Persistent: one wave per SIMD (the recovery's register footprint allows no
 // more) walks 64-cell chunks q, q + W, ...; the loads of the next chunk are
 // in flight while the current chunk's recovery runs.
-struct StageIn {
-    long o;
-    bool ok;
-    double P[NF], Un[NF], rh[NF], Us[NF], R1[3], R2[3], sg, a, g[6], K[6];
-};
 
 // Inputs of a stage kernel as a list of streams (array, field), each one
 // [Np] row of doubles.  STAGE 1: U^n, the (p, v) guess, sigma, metric;
@@ -1189,7 +1282,7 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
     __builtin_amdgcn_sched_barrier(0);
-    if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
+    if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.tolq, p.maxit, &it);
     else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     __builtin_amdgcn_sched_barrier(0);
     tally_cell(tal, p.hist != nullptr, in.ok, st, it);
@@ -1210,7 +1303,7 @@ __device__ __forceinline__ void stage1_cell(const Params& p, double dt, const St
 // guessed from P^{n+1} into P1o and Ro (to rounding, the results of stage1_cell on the
 // stored U^{n+1} and P^{n+1}: the same recovery on the same inputs, which the
 // plain recovery's setup already holds), tallied in tal1.
-template <int STAGE, bool CURVED, bool HASK, bool DG>
+template <int STAGE, bool CURVED, bool HASK, bool DG, bool MODEL>
 __device__ __forceinline__ void update_cell(const Params& p, double dt, const StageIn& in, double* __restrict__ Uo,
                                             double* __restrict__ Po, double* __restrict__ Ro,
                                             double* __restrict__ P1o, int* __restrict__ status, long st_stride,
@@ -1270,8 +1363,8 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
     double E[3] = {k.Es[0], k.Es[1], k.Es[2]};
     int it, st;
     if (STAGE == 2) {
-        k.cfac = g * dt * m.alp * (p.sig_model ? sigma_of_D(p, YD) : in.sg);
-        if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.maxit, &it);
+        k.cfac = g * dt * m.alp * ((MODEL && p.sig_model) ? sigma_of_D(p, YD) : in.sg);
+        if (k.cfac != 0.0) st = recover_stiff(k, x, E, p.tol, p.tolq, p.maxit, &it);
         else st = recover_plain(k, E, x, p.tol, p.maxit, &it);
     } else {
         st = recover_plain(k, E, x, p.tol, p.maxit, &it);
@@ -1301,11 +1394,11 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
         // failed cell keeps the guess and E^{n+1}, as in stage1_cell
         __builtin_amdgcn_sched_barrier(0);
         const double gdt = g * dt;
-        k.cfac = gdt * m.alp * (p.sig_model ? sigma_of_D(p, YD) : in.sg);
+        k.cfac = gdt * m.alp * ((MODEL && p.sig_model) ? sigma_of_D(p, YD) : in.sg);
         const double xg[4] = {x[0], x[1], x[2], x[3]};
         double E1[3] = {k.Es[0], k.Es[1], k.Es[2]};
         int it1, st1;
-        if (k.cfac != 0.0) st1 = recover_stiff(k, x, E1, p.tol, p.maxit, &it1);
+        if (k.cfac != 0.0) st1 = recover_stiff(k, x, E1, p.tol, p.tolq, p.maxit, &it1);
         else st1 = recover_plain(k, E1, x, p.tol, p.maxit, &it1);
         __builtin_amdgcn_sched_barrier(0);
         tally_cell(tal1, p.hist != nullptr, in.ok, st1, it1);

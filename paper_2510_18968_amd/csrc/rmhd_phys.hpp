@@ -765,14 +765,17 @@ __device__ __forceinline__ int rec_jacobian(const RecInT<double, DG>& k, const d
 // with the exact Jacobian, kept between iterations while the steps contract
 // fast (chord steps) and refreshed otherwise; backtracking keeps the state
 // physical and the residual decreasing.  x in/out: guess -> (p, v^i);
-// E out: densitised E at the root.
+// E out: densitised E at the root.  tolq = 0.0075 tol (the early stop).
 template <bool DG>
-__device__ int recover_stiff(const RecInT<double, DG>& k, double* x, double* E, double tol, int maxit, int* iters) {
+__device__ int recover_stiff(const RecInT<double, DG>& k, double* x, double* E, double tol, double tolq, int maxit,
+                             int* iters) {
     if (!(k.D > 0.0) || !isfinite(k.tau) || !(x[0] > 0.0)) { *iters = 0; return ST_UNPHYS; }
     double r[4], Ji[4][4];
     int it = 0, restart = 0;
-    bool need = true, fresh = false;
-    double last_rel = 1e300, prev_step = 1e300;
+    bool need = true, fresh = false, have_prev = false;
+    // (flags and inline constants rather than a 1e300 sentinel: the compiler
+    // keeps such a literal in two registers across the whole kernel)
+    double last_rel = 1.0, prev_step = 0.0;
     // one call site each for the Jacobian and the residual keeps the code of
     // the stage kernels within the instruction cache
     for (;;) {
@@ -823,13 +826,14 @@ __device__ int recover_stiff(const RecInT<double, DG>& k, double* x, double* E, 
         // a full step that contracted by q < 1/4 leaves an error of at most
         // about q step / (1 - q): once that is below tol / 100 the next step
         // would only confirm convergence, so stop here
-        if (t == 1.0 && prev_step < 1e300 && step <= 0.25 * prev_step && step * step <= 0.0075 * tol * prev_step) {
+        if (t == 1.0 && have_prev && step <= 0.25 * prev_step && step * step <= tolq * prev_step) {
             *iters = it;
             return ST_OK;
         }
-        if (t < 1.0 || step > 0.25 * prev_step) need = true;
+        if (t < 1.0 || (have_prev && step > 0.25 * prev_step)) need = true;
         else fresh = false;
         prev_step = step;
+        have_prev = isfinite(step);
     }
     *iters = maxit;
     return last_rel <= 1e-12 ? ST_WARN : ST_NOCONV;
@@ -859,7 +863,7 @@ __device__ int recover_plain(const RecInT<double, DG>& k, const double* Ec, doub
     }
     const double s2 = dot3(sm, smu);
     double p = x[0];
-    double last_rel = 1e300;
+    double last_rel = 1.0;                       // (set by every iteration)
     const double G = k.G;
     const double iD = 1.0 / k.D;
     for (int it = 1; it <= maxit; ++it) {

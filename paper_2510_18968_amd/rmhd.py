@@ -26,7 +26,8 @@ SYMBOLS = ("rmhd_workspace_bytes", "rmhd_padded_extent", "rmhd_init_grid", "rmhd
            "rmhd_step_adjoint", "rmhd_prim2con_adjoint", "rmhd_recovery_stats", "rmhd_recovery_stats_read", "rmhd_set_stream",
            "rmhd_step_adjoint_static", "rmhd_atmosphere_cells", "rmhd_steps")
 HIST_BINS = 32
-TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other")
+TIMING_CLASSES = ("ghost_fill", "flux_x", "flux_y", "flux_z", "update_stage2", "update_final", "stage1", "other",
+                  "flux_z_update_stage2")
 
 
 class GridDesc(C.Structure):

@@ -1,6 +1,8 @@
 // Instantiates every stage kernel (the fused final update + stage 1 too),
 // the FP64 x-flux kernels and y/z window kernels (general and diagonal
-// metric) so that their gfx950 assembly can be checked (tests/test_stage_waits.py); never linked into the library.
+// metric; the z window with the stage-2 update too) so that their gfx950
+// assembly can be checked (tests/test_stage_waits.py); never linked into the
+// library.
 #include <hip/hip_runtime.h>
 #include "rmhd_kernels.hpp"
 using namespace rmhd;
@@ -31,4 +33,10 @@ void all(const Params& p, double* a, unsigned long long* c, int* s) {
     inst_x<0, true, false>(p, a); inst_x<1, true, false>(p, a); inst_x<2, true, false>(p, a);
     inst_x<0, true, true>(p, a); inst_x<1, true, true>(p, a); inst_x<2, true, true>(p, a);
     stages<1>(p, a, c, s); stages<2>(p, a, c, s); stages<3>(p, a, c, s); stages<4>(p, a, c, s);
+}
+template <int RC, bool C, bool DG> void inst_f(const Params& p, double* a) {
+    k_flux_w<2, RC, C, double, false, DG, true><<<8, 64>>>(p, a, a, a, 32, 1, 1, FuseArgs{});
+}
+void all_f(const Params& p, double* a) {
+    inst_f<1, true, true>(p, a); inst_f<0, true, true>(p, a); inst_f<1, false, false>(p, a);
 }

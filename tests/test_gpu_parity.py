@@ -40,7 +40,11 @@ def host(t):
 def small_workloads():
     mode1 = W.curved_blob(n=16, recon="mc2", steps=2, shift=0.05)
     mode1.extra["speed_mode"] = 1      # alpha sqrt(gamma^dd) -+ beta^d
+    box_mc2 = W.periodic_box(n=12, steps=2)
+    box_mc2.recon = W.RECON["mc2"]     # flat 3D MC2: the z sweep runs the stage-2 update
+    box_mc2.name = "periodic_box_12^3_mc2"
     return {
+        "box12_mc2": box_mc2,
         "shocktube_s1e6": W.shocktube(seed=103, sigma0=1e6),
         "shocktube_s1": W.shocktube(seed=101, sigma0=1.0),
         "box12": W.periodic_box(n=12, steps=2),
@@ -180,6 +184,7 @@ def run_oracle(orc, w, steps):
                                                 ("shocktube_s1e6", 20, 1), ("blob16_shift_weno5", 3, 1),
                                                 ("blob16_shift_mode1", 3, 1), ("slicing16_weno5", 3, 1),
                                                 ("slicing32_2d_mc2", 4, 0), ("cylexp40_minmod", 6, 1),
+                                                ("box12_mc2", 3, 1), ("blob20_minmod", 3, 1), ("blob20_mc2", 3, 1),
                                                 ("cylexp40_minmod", 6, 0), ("batch64x2048", 3, 1)])
 def test_multi_step_parity(R, orc, name, steps, x_align):
     """Several whole steps against the oracle.  batch64x2048 is the full

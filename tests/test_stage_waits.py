@@ -60,14 +60,17 @@ def test_kernel_waits_cover_their_loads(asm, kind, count, load):
 
 def test_window_kernel_waits_cover_their_loads(asm):
     ks = {k: v for k, v in asm.items() if "k_flux_w" in k}
-    assert len(ks) == 12
+    assert len(ks) == 15
     for name, L in ks.items():
-        m = re.search(r"k_flux_wILi(\d)ELi(\d)ELb(\d)E([df])Lb(\d)ELb(\d)E", name)
+        m = re.search(r"k_flux_wILi(\d)ELi(\d)ELb(\d)E([df])Lb(\d)ELb(\d)ELb(\d)E", name)
         curved, shift, diag = m.group(3) == "1", m.group(5) == "1", m.group(6) == "1"
-        # rhs stores, the staging row (sigma, alpha, gamma_ij -- its diagonal
-        # on a diagonal metric --, beta^i, in pairs), rhs reads
+        fuse = m.group(7) == "1"
+        # the step's stores (rhs row, or the stage update's 32), the staging
+        # row (sigma, alpha, gamma_ij -- its diagonal on a diagonal metric --,
+        # beta^i, in pairs), rhs reads
         nstage = (2 + (3 if diag else 6) + (3 if shift else 0) + 1) // 2 if curved else 1
-        n_ring = 14 + nstage + 14
+        # (fused: the update's 17 loads too; vmcnt holds at most 63)
+        n_ring = min(63, 32 + nstage + 14 + 17) if fuse else 14 + nstage + 14
         dma = [i for i, l in enumerate(L) if "global_load_lds_dwordx4" in l]
         heads = [i for i, l in enumerate(L) if "Loop Header" in l and i < dma[-1]]
         assert dma and heads, name
@@ -78,6 +81,17 @@ def test_window_kernel_waits_cover_their_loads(asm):
             lo, hi = path_counts(L, dma[-1] + 1, w)
             print(f"{name[:44]}: vmcnt({n_ring}) after the ring load: {lo}..{hi}")
             assert lo is not None and lo >= n_ring, (name, lo)
+        if fuse:
+            # the rhs row and the update's U^n and R1 rows at the top of the
+            # step, then the wait before the update (ring row c + 3 behind them)
+            loads = [i for i, l in enumerate(L) if "global_load_dwordx2" in l and i > heads[-1]][:31]
+            waits = [i for i, l in enumerate(L) if "s_waitcnt vmcnt(7)" in l and i > loads[-1]]
+            assert len(loads) == 31 and waits, (name, len(loads))
+            for w in waits:
+                lo, hi = path_counts(L, loads[-1] + 1, w)
+                print(f"{name[:44]}: vmcnt(7) after the update's loads: {lo}..{hi}")
+                assert lo is not None and lo >= 7, (name, lo)
+            continue
         # rhs row: the 14 loads after the loop head, then the wait before the stores
         rhs = [i for i, l in enumerate(L) if "global_load_dwordx2" in l and i > heads[-1]][:14]
         rhs_waits = [i for i, l in enumerate(L) if "s_waitcnt vmcnt(7)" in l and i > rhs[-1]]
@@ -89,19 +103,25 @@ def test_window_kernel_waits_cover_their_loads(asm):
 
 
 def loop_full_waits(L):
-    """Lines in loop blocks (the compiler's "in Loop" label comments) that wait for every vector memory op."""
+    """Lines in loop blocks (the compiler's "in Loop" label comments) that wait
+    for every vector memory op.  Not counted: a wait right before an LDS
+    atomic of the fused window's stage tally, which sits in the same LDS
+    object as the ring and runs only on a failed cell or with the iteration
+    histogram on."""
     hits, inloop = [], False
     for i, l in enumerate(L):
         if re.match(r"^(\.LBB\S+:|; %bb\.\d+:)", l):
             inloop = "Loop" in l
         if inloop and re.search(r"s_waitcnt\s.*vmcnt\(0\)", l):
+            if i + 1 < len(L) and "ds_add_u32" in L[i + 1]:
+                continue
             hits.append(i)
     return hits
 
 
 def test_no_full_wait_inside_sweep_loops(asm):
     ks = {k: v for k, v in asm.items() if "k_flux_w" in k or "k_flux_p" in k}
-    assert len(ks) == 21
+    assert len(ks) == 24
     checked = 0
     for name, L in ks.items():
         if any("scratch_" in l for l in L):
