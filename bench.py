@@ -73,8 +73,8 @@ BYTES_PER_CELL = {
     # ghost layers only
     "ghost_fill": 0,
 }
-FLOPS_PER_CELL = {"flux_x": 2576.1, "flux_y": 2339.6, "flux_z": 2341.6, "update_stage2": 1693.4}
-TRAFFIC_BYTES_PER_CELL = {"flux_x": 178.1 + 120.1, "flux_y": 268.3 + 112.0, "flux_z": 268.3 + 112.0,
+FLOPS_PER_CELL = {"flux_x": 2576.1, "flux_y": 2339.5, "flux_z": 2341.6, "update_stage2": 1688.6}
+TRAFFIC_BYTES_PER_CELL = {"flux_x": 178.0 + 120.1, "flux_y": 268.3 + 112.0, "flux_z": 268.3 + 112.0,
                           "update_stage2": 344.3 + 248.0}
 
 
