@@ -128,7 +128,10 @@ enum rmhd_sigma_model { RMHD_SIGMA_FIELD = 0, RMHD_SIGMA_POWER = 1, RMHD_SIGMA_D
  *                              out U_out = U(2), P_out = P(2), R_out = R2
  *   stage 3 (final update):    in U_n, U_s = U(2), P_in = P(2), R1, R2
  *                              out U_out = U^{n+1}, P_out = P^{n+1}
- * Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  Stage 2 may
+ * Stage 2's local sources take the densitised cleaning fields (phi, psi, q)
+ * of U(1) from U_n (stage 1 changes only E), the final update those of U(2)
+ * from U_s: only p and v of P_in are read at the cell (with zero extrinsic
+ * curvature).  Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  Stage 2 may
  * also overwrite the x ghost cell next to the interior of each row of U_out,
  * P_out, R_out and status (when n_x is not a multiple of 64).  For stage 3,
  * U_out may alias U_n and P_out may alias nothing else.  status is optional

@@ -1118,8 +1118,10 @@ __device__ __forceinline__ void sources_t(const Params& p, const Geo<double>& m,
 // [Np] row of doubles.  STAGE 1: U^n, the (p, v) guess, sigma, metric;
 // 2: + P(1), rhs, R1, K; 3: P(2), U^n, U(2), rhs, R1, R2, metric, K;
 // 4 (the final update followed by the next step's stage 1): 3 + sigma.
-// Without K the local sources need only v and the cleaning fields of P_s,
-// and the guess p and v: the other seven primitives are not loaded.
+// Without K the local sources need only v and the densitised cleaning fields
+// of the stage state, which are U^n's (stage 2: stage 1 leaves them as they
+// are) or U(2)'s (final update), and the guess p and v: of P_s only p and v
+// are loaded.
 enum : int { SA_UN, SA_US, SA_PS, SA_R1, SA_R2, SA_RHS, SA_SIG, SA_ALP, SA_GAM, SA_K };
 struct StreamList {
     int n;
@@ -1136,7 +1138,6 @@ template <int STAGE, bool CURVED, bool HASK, bool DG> __host__ __device__ conste
             for (int f = 0; f < NF; ++f) add(SA_PS, f);
         } else {
             for (int f = I_P; f < I_V + 3; ++f) add(SA_PS, f);
-            for (int f = I_PHI; f < NF; ++f) add(SA_PS, f);
         }
         for (int f = 0; f < NF; ++f) add(SA_RHS, f);
         for (int i = 0; i < 3; ++i) add(SA_R1, i);
@@ -1324,8 +1325,10 @@ __device__ __forceinline__ void update_cell(const Params& p, double dt, const St
             if (HASK) {
                 prim2con(m, p.G, in.P, Uc);
             } else {
-                // the densitised cleaning fields, all the local sources read
-                for (int f = I_PHI; f < NF; ++f) Uc[f] = in.P[f] * m.sg;
+                // the densitised cleaning fields of the stage state, all the
+                // local sources read besides v: U^n's in stage 2 (U(1) differs
+                // from U^n in E only), U(2)'s in the final update
+                for (int f = I_PHI; f < NF; ++f) Uc[f] = STAGE == 2 ? in.Un[f] : in.Us[f];
             }
             sources_local<CURVED>(p, m, in.K, CURVED && HASK, in.P, Uc, S);
             if (STAGE == 2) {
