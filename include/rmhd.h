@@ -38,7 +38,9 @@
  *    at cell centres INCLUDING ghost cells (the caller evaluates them there).
  *  - Every call is asynchronous on the context's HIP stream, except those
  *    documented as synchronising.  Only interior cells of outputs are
- *    written; ghost cells of U are never read.
+ *    written (stage 2's exception: rmhd_stage_bufs); ghost cells of U and
+ *    of the primitives are never read (the flux sweeps take a ghost cell's
+ *    primitives and sigma at its interior image, the boundary conditions).
  *  - Return codes: RMHD_OK or a negative RMHD_E* code.  Argument checks
  *    happen on the host before any device work (RMHD_EINVAL).  Per-cell
  *    recovery failures never abort a launch: they set a per-cell status and
@@ -131,7 +133,9 @@ enum rmhd_sigma_model { RMHD_SIGMA_FIELD = 0, RMHD_SIGMA_POWER = 1, RMHD_SIGMA_D
  * Stage 2's local sources take the densitised cleaning fields (phi, psi, q)
  * of U(1) from U_n (stage 1 changes only E), the final update those of U(2)
  * from U_s: only p and v of P_in are read at the cell (with zero extrinsic
- * curvature).  Stages 2 and 3 overwrite P_in's ghost cells (ghost fill).  Stage 2 may
+ * curvature).  Stages 2 and 3 read no ghost cell of P_in: the flux sweeps take
+ * a ghost cell's primitives at its interior image (the boundary conditions
+ * of the descriptor), and P_in is not written.  Stage 2 may
  * also overwrite the x ghost cell next to the interior of each row of U_out,
  * P_out, R_out and status (when n_x is not a multiple of 64).  For stage 3,
  * U_out may alias U_n and P_out may alias nothing else.  status is optional
@@ -281,11 +285,12 @@ int rmhd_recovery_stats_read(rmhd_ctx* ctx, int64_t* bins_out);
 
 /* Opt-in per-kernel timing (profiling aid, off by default): with enable != 0
  * the library brackets every launch with HIP events on the context's stream,
- * grouped by kernel class: 0 ghost fill, 1 x fluxes, 2 y fluxes, 3 z fluxes,
- * 4 stage-2 update + stiff recovery, 5 final update + recovery, 6 stage 1,
- * 7 other pointwise kernels, 8 z fluxes with the stage-2 update of each
- * finished row (stage 2 on 3D grids without extrinsic curvature, which then
- * has no class-4 launch).  rmhd_timing_read synchronises the stream,
+ * grouped by kernel class: 0 ghost fill (the adjoint's), 1 x fluxes, 2 y
+ * fluxes, 3 z fluxes, 4 stage-2 update + stiff recovery, 5 final update +
+ * recovery, 6 stage 1, 7 other pointwise kernels, 8 z fluxes with the
+ * stage-2 update of each finished row (stage 2 on 3D grids in FP64 with MC2
+ * or minmod, a flat or diagonal metric without shift or K and a sigma field,
+ * which then has no class-4 launch).  rmhd_timing_read synchronises the stream,
  * writes the summed milliseconds and launch counts of each class since the
  * last read (arrays of RMHD_TIMING_CLASSES entries) and resets them.  If an
  * event could not be created or recorded since the last read, it resets the

@@ -184,14 +184,12 @@ unsigned nblk(long n, int b) { return (unsigned)((n + b - 1) / b); }
 
 int ghost_fill(rmhd_ctx* c, double* a, int nf) {
     const Params& p = c->p;
-    for (int d = 0; d < 3; ++d) {
-        if (!is_active(p, d)) continue;
-        const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
-        const long tot = 2L * p.ng * p.n[e1] * p.n[e2] * nf;
-        Timed t(c, T_GHOST);
-        k_ghost<<<nblk(tot, 256), 256, 0, c->stream>>>(p, a, nf, d);
-        LAUNCH_CHECK();
-    }
+    const long tot = (ghost_count(p, 0) + ghost_count(p, 1) + ghost_count(p, 2)) * nf;
+    if (tot == 0) return RMHD_OK;
+    Timed t(c, T_GHOST);
+    if (tot < (1L << 31)) k_ghost<unsigned><<<nblk(tot, 256), 256, 0, c->stream>>>(p, a, nf);
+    else k_ghost<unsigned long><<<nblk(tot, 256), 256, 0, c->stream>>>(p, a, nf);
+    LAUNCH_CHECK();
     return RMHD_OK;
 }
 
@@ -359,7 +357,8 @@ int flux_sigma(rmhd_ctx* c, const double* P, const double* sig, const double** o
 int stage2(rmhd_ctx* c, double dt, const double* sig, const double* Un, double* P1, const double* R1, double* U2,
            double* P2, double* R2, int32_t* st) {
     int r;
-    if ((r = ghost_fill(c, P1, NF)) != RMHD_OK) return r;
+    // (no ghost fill: the sweeps read a ghost cell's primitives at its
+    // interior image, as they do sigma)
     const double* fs = nullptr;
     if ((r = flux_sigma(c, P1, sig, &fs)) != RMHD_OK) return r;
     // The z sweep with the update in one kernel measured faster for FP64
@@ -385,7 +384,6 @@ int stage2(rmhd_ctx* c, double dt, const double* sig, const double* Un, double* 
 int stage3(rmhd_ctx* c, double dt, const double* sig, const double* Un, const double* U2, double* P2,
            const double* R1, const double* R2, double* Uo, double* Po, int32_t* st) {
     int r;
-    if ((r = ghost_fill(c, P2, NF)) != RMHD_OK) return r;
     const double* fs = nullptr;
     if ((r = flux_sigma(c, P2, sig, &fs)) != RMHD_OK) return r;
     if ((r = flux_div(c, P2, fs)) != RMHD_OK) return r;
@@ -396,7 +394,6 @@ int stage3(rmhd_ctx* c, double dt, const double* sig, const double* Un, const do
 // stage 1 into the workspace's P(1) and R1 (R1 read and rewritten per cell)
 int stage3_then_stage1(rmhd_ctx* c, double dt, const double* sig, double* U, double* P) {
     int r;
-    if ((r = ghost_fill(c, c->P2, NF)) != RMHD_OK) return r;
     const double* fs = nullptr;
     if ((r = flux_sigma(c, c->P2, sig, &fs)) != RMHD_OK) return r;
     if ((r = flux_div(c, c->P2, fs)) != RMHD_OK) return r;
@@ -538,6 +535,8 @@ int rmhd_step_adjoint(rmhd_ctx* c, double dt, const double* sigma, const double*
     // forward recompute of the stages
     if ((r = stage1(c, dt, sigma, U_n, P_n, c->P1, c->R1, nullptr, nullptr)) != RMHD_OK) return r;
     if ((r = stage2(c, dt, sigma, U_n, c->P1, c->R1, c->U2, c->P2, c->R2, nullptr)) != RMHD_OK) return r;
+    // the adjoint's face kernels read the stage primitives at ghost cells
+    if ((r = ghost_fill(c, c->P1, NF)) != RMHD_OK) return r;
     if ((r = ghost_fill(c, c->P2, NF)) != RMHD_OK) return r;
     // reverse sweep
     const long n = ncells(c->p);

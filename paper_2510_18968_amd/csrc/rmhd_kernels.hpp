@@ -251,8 +251,11 @@ template <int D, bool CURVED, bool DG>
 __device__ __forceinline__ void flux_load(const Params& p, const double* __restrict__ P,
                                           const double* __restrict__ sig, const FluxItem<D>& it, FluxIn& in) {
     const long Np = p.Np, o = it.o;
+    // a ghost cell's primitives and sigma from its interior image (boundary
+    // conditions; the metric is given at ghost cells)
+    const long oi = o + (long)(bc_map(p, D, it.cp) - it.cp) * p.st[D];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) in.P[f] = P[f * Np + o];
+    for (int f = 0; f < NF; ++f) in.P[f] = P[f * Np + oi];
     if (CURVED) {
 #pragma unroll
         for (int a = 0; a < 6; ++a)
@@ -263,7 +266,7 @@ __device__ __forceinline__ void flux_load(const Params& p, const double* __restr
             for (int a = 0; a < 3; ++a) in.b[a] = p.bet[a * Np + o];
         }
     }
-    in.s = sig[o + (long)(bc_map(p, D, it.cp) - it.cp) * p.st[D]];
+    in.s = sig[oi];
 }
 
 // minus the D-flux divergence of one segment into rhs (= or +=)
@@ -554,8 +557,10 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     const double cd = p.cdiff[D];
     auto slot = [&](int c) { return (c + gD) % WRING; };
     auto ringP = [&](int c, int f) -> double { return ring[(slot(c) * NF + f) * 64 + lane]; };
-    auto load_ring = [&](int c) {
-        const double* src = P + (long)fhalf * Np + rowb + (long)(c + gD) * s + xpair;
+    // row c into its ring slot; r: the padded row it is read from (a ghost
+    // row's interior image, the boundary conditions)
+    auto load_ring = [&](int c, int r) {
+        const double* src = P + (long)fhalf * Np + rowb + (long)r * s + xpair;
         double* dst = ring + slot(c) * NF * 64;
 #pragma unroll
         for (int f = 0; f < NF; f += 2)
@@ -617,7 +622,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
     // window of the first step (c = c0 - 1): P rows c0-3 .. c0+1, metric rows
     // c0-4 .. c0 (row c0-4 is outside the padding when c0 = 0 and unused),
     // staging row c0 + 1
-    for (int c = c0 - 3; c <= c0 + 1; ++c) load_ring(c);
+    for (int c = c0 - 3; c <= c0 + 1; ++c) load_ring(c, bc_map(p, D, c + gD));
     load_stage(c0 + 1);
     for (int k = 0; k < 5; ++k) {
         const int c = c0 - 4 + k;
@@ -649,6 +654,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
 #pragma unroll 1
     for (int c = c0 - 1; c <= c1; ++c) {
         const int cnext = min(c + 3, nD + 2);           // row c + 3, clamped inside the padding
+        const int rnext = bc_map(p, D, cnext + gD);     // the row it is read from
         const bool fin = c - 1 >= c0;                   // rhs of c - 1 is finished this step
         const long om = base + (long)(c - 1 + gD) * s;
         double acc[NF];
@@ -719,7 +725,7 @@ __global__ __launch_bounds__(64) void k_flux_w(const Params p, const double* __r
         // row c - 2 is consumed: request row c + 3 into its slot
         __builtin_amdgcn_sched_barrier(0);
         asm volatile("" ::: "memory");
-        load_ring(cnext);
+        load_ring(cnext, rnext);
         {
             // (the first step's face is not needed: computed, and stored to the ghost cell)
             // face c - 1/2: metric at the face from rows c-2 .. c+1 (window 1..4)
@@ -828,21 +834,54 @@ __global__ void k_any_nonzero(const double* __restrict__ a, long n, unsigned lon
 
 // ---------------------------------------------------------------- ghost fill
 // faces only: the ng ghost layers next to the interior along each active d,
-// interior extents elsewhere
+// interior extents elsewhere; all active directions in one launch (the
+// faces do not overlap: each copies interior-extent cells of its own d)
 // (one thread per ghost cell and field: the copies are independent)
-__global__ void k_ghost(const Params p, double* __restrict__ a, int nf, int d) {
+__host__ __device__ inline long ghost_count(const Params& p, int d) {
+    if (!((p.active >> d) & 1)) return 0;
     const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
-    const long n1 = p.n[e1], n2 = p.n[e2];
-    const long tot = 2L * p.ng * n1 * n2;
-    long t = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= tot * nf) return;
-    const int f = (int)(t / tot);
-    t -= (long)f * tot;
-    const int a1 = (int)(t % n1) + p.g[e1];
-    t /= n1;
-    const int a2 = (int)(t % n2) + p.g[e2];
-    t /= n2;
-    const int layer = (int)t;   // 0..2ng-1
+    return 2L * p.ng * p.n[e1] * p.n[e2];
+}
+// I: the index type of the decomposition (32-bit when the thread count fits:
+// 64-bit division is a long instruction sequence on the GPU)
+template <class I>
+__global__ void k_ghost(const Params p, double* __restrict__ a, int nf) {
+    I t = (I)((long)blockIdx.x * blockDim.x + threadIdx.x);
+    int d = 0;
+    I tot = (I)ghost_count(p, 0) * (I)nf;
+    if (t >= tot) {
+        t -= tot;
+        d = 1;
+        tot = (I)ghost_count(p, 1) * (I)nf;
+        if (t >= tot) {
+            t -= tot;
+            d = 2;
+            tot = (I)ghost_count(p, 2) * (I)nf;
+            if (t >= tot) return;
+        }
+    }
+    tot /= (I)nf;
+    const int e1 = (d == 0) ? 1 : 0, e2 = (d == 2) ? 1 : 2;
+    const I n1 = (I)p.n[e1], n2 = (I)p.n[e2];
+    int f, a1, a2, layer;       // layer 0..2ng-1
+    if (d == 0) {
+        // x faces: the layers of one row next to each other (x is contiguous)
+        const I nl = (I)(2 * p.ng);
+        layer = (int)(t % nl);
+        t /= nl;
+        a1 = (int)(t % n1) + p.g[e1];
+        t /= n1;
+        a2 = (int)(t % n2) + p.g[e2];
+        f = (int)(t / n2);
+    } else {
+        // y, z faces: x runs along the threads
+        f = (int)(t / tot);
+        t -= (I)f * tot;
+        a1 = (int)(t % n1) + p.g[e1];
+        t /= n1;
+        a2 = (int)(t % n2) + p.g[e2];
+        layer = (int)(t / n2);
+    }
     const int c = layer < p.ng ? p.g[d] - p.ng + layer : p.g[d] + p.n[d] + layer - p.ng;
     const int src = bc_map(p, d, c);
     const long ob = (long)a1 * p.st[e1] + (long)a2 * p.st[e2];
