@@ -503,11 +503,12 @@ struct FuseArgs {
 
 // SHIFT: the metric has a shift (beta rows in the window); without one the
 // window holds alpha, gamma_ij and sigma only.  DG: a diagonal metric, whose
-// window and staging row hold the three diagonal entries of gamma_ij.  FUSE
-// (D = 2, no extrinsic curvature, a sigma field): instead of storing rhs row c - 1, the
-// step runs stage 2 on its cells (update_cell on U^n and R1 loaded for the
-// row, P(1) from the ring, metric and sigma from the window), so the 14-word
-// rhs, P(1), metric and sigma of the stage update make no HBM round trip.
+// window and staging row hold the three diagonal entries of gamma_ij.
+// FUSE (D = 2, no extrinsic curvature, a sigma field): instead of storing rhs
+// row c - 1, the step runs stage 2 on its cells (update_cell on U^n and R1
+// loaded for the row, P(1) from the ring, metric and sigma from the window),
+// so the 14-word rhs, P(1), metric and sigma of the stage update make no HBM
+// round trip.
 // A step with no finished row (the first of a segment) sends its 32 stores
 // to an x ghost cell of rhs, which nothing reads; lanes past x's end write
 // the x ghost cell next to the interior of U2, P2, R2 (and status).
