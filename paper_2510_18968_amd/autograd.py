@@ -1,9 +1,10 @@
 """Differentiable rollout of the IMEX step: torch.autograd.Function wrappers
 over the library's forward and adjoint entry points (no arithmetic here).
 
-RMHDRollout runs n IMEX steps keeping (U, P) every `ckpt` steps; backward
-recomputes each segment forward from its checkpoint and applies
-rmhd_step_adjoint step by step in reverse.  Prim2Con maps primitives to
+RMHDRollout runs n IMEX steps keeping (U, P) every `ckpt` steps (one
+rmhd_steps call per segment); backward recomputes each segment forward from
+its checkpoint with rmhd_step and applies rmhd_step_adjoint step by step in
+reverse.  Prim2Con maps primitives to
 conserved variables with rmhd_prim2con / rmhd_prim2con_adjoint.
 """
 from __future__ import annotations
@@ -31,10 +32,11 @@ class RMHDRollout(torch.autograd.Function):
         P = P0.detach().clone()
         sig = sigma.detach().contiguous()
         checkpoints = []
-        for n in range(nsteps):
-            if n % ckpt == 0:
-                checkpoints.append((U.clone(), P.clone()))
-            grid.step(dt, sig, U, P)
+        # each segment in one rmhd_steps call (every final update runs the
+        # next step's stage 1); backward recomputes the segment step by step
+        for n0 in range(0, nsteps, ckpt):
+            checkpoints.append((U.clone(), P.clone()))
+            grid.steps(dt, sig, U, P, min(ckpt, nsteps - n0))
         if grid.failures():
             raise RuntimeError("recovery failures in the forward rollout")
         ctx.grid, ctx.dt, ctx.nsteps, ctx.ckpt = grid, dt, nsteps, ckpt
