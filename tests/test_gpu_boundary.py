@@ -66,3 +66,37 @@ def test_ghost_cells_of_the_stage_input_are_not_read(R, name, x_align):
         assert bool(torch.isfinite(b).all()), (name, k)
         assert torch.equal(a, b), (name, k, float((a - b).abs().max()))
     print(f"[boundary] {name}: stages 2 and 3 bitwise equal with NaN ghost cells in P_in", flush=True)
+
+
+@pytest.mark.parametrize("recon", ["weno5", "mc2"])
+def test_stage2_status_array(R, recon):
+    """stage 2 with a status array (the MC2 run takes the z sweep with the
+    update): the same outputs as without it, every interior status 0 or 1,
+    and no status cell written outside the interior but the x ghost cell
+    next to it (the header's allowance for rows whose end is not a multiple
+    of 64 cells)"""
+    w = W.curved_blob(n=20, recon=recon)
+    g = R.grid_for(w, x_align=1)
+    g.set_metric(g.to_layout(w.metric))
+    sig = g.to_layout(w.sigma)
+    Pn = g.to_layout(w.P)
+    Un = g.prim2con(Pn)
+    P1, R1 = g.empty(), g.empty(3)
+    g.imex_stage(1, w.dt, sig, Un, Pn, P1, R_out=R1)
+    outs = []
+    st = torch.full(g.padded, 7, dtype=torch.int32, device="cuda")
+    for status in (None, st):
+        U2, P2, R2 = g.empty(), g.empty(), g.empty(3)
+        g.imex_stage(2, w.dt, sig, Un, P1, P2, R_out=R2, R1=R1, U_out=U2, status=status)
+        outs.append((U2, P2, R2))
+    torch.cuda.synchronize()
+    assert g.failures() == 0
+    inner = interior_mask(g, w)
+    for a, b in zip(*outs):
+        assert torch.equal(a[:, inner], b[:, inner])
+    s_in = st[inner]
+    assert bool(((s_in == 0) | (s_in == 1)).all()), torch.unique(s_in)
+    allowed = inner.clone()
+    gx = g.ghosts[0]
+    allowed[:, :, gx - 1] = True          # the x ghost cell next to the interior
+    assert bool((st[~allowed] == 7).all())
